@@ -1,0 +1,202 @@
+"""CPU oracle for the kNN and friends-of-friends results (TEST INFRASTRUCTURE).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package. It is a plain, slow, obviously correct
+implementation of what the GPU library computes, written from the paper's
+problem statements and sharing no code with the GPU library:
+
+* ``knn_bf`` / ``fof_bf``: the definitions written out (all pairs).
+* ``knn_kd`` / ``fof_kd``: exact kd-tree accelerations for large inputs, pinned
+  bit-for-bit to the brute-force versions by the tests.
+* ``components_uf`` / ``components_bfs``: two independent component labelings
+  of an explicit edge list.
+* :mod:`oracle.planes`: the tree-plane construction of the paper's section on
+  the plane-based hierarchy (gap levels, node sizes, split selection), pinned to
+  the paper's worked example (Fig. 3).
+
+Fixed arithmetic (the paper fixes only float32 precision; this reading is shared
+with the GPU side): ``dist2 = fl(fl(fl(dx*dx) + fl(dy*dy)) + fl(dz*dz))`` with
+``dx = fl(x_i - x_j)`` etc., IEEE binary32, no FMA, subnormals kept. kNN rows
+are ordered by (dist2, index); FoF links pairs with ``dist2 <= fl(b*b)``;
+labels are the smallest member index.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_f32p = ctypes.POINTER(ctypes.c_float)
+
+
+def default_threads() -> int:
+    """Threads for the oracle: the process's CPU share, capped by OMP_NUM_THREADS."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        n = os.cpu_count() or 1
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, n)
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_build.LIB) or (
+            os.path.getmtime(_build.LIB) < os.path.getmtime(_build.SRC)):
+        _build.build()
+    lib = ctypes.CDLL(_build.LIB)
+    lib.jzo_knn_bf.argtypes = [_f32p, ctypes.c_int64, ctypes.c_int, _i64p, ctypes.c_int64,
+                               _i32p, _f32p, ctypes.c_int]
+    lib.jzo_knn_kd.argtypes = lib.jzo_knn_bf.argtypes
+    lib.jzo_fof_bf.argtypes = [_f32p, ctypes.c_int64, ctypes.c_float, _i32p, ctypes.c_int]
+    lib.jzo_fof_kd.argtypes = lib.jzo_fof_bf.argtypes
+    lib.jzo_components_uf.argtypes = [ctypes.c_int64, _i32p, ctypes.c_int64, _i32p]
+    lib.jzo_components_bfs.argtypes = lib.jzo_components_uf.argtypes
+    lib.jzo_range_rows_bf.argtypes = [_f32p, ctypes.c_int64, ctypes.c_float, _i64p,
+                                      ctypes.c_int64, ctypes.c_int64, _i64p, _i32p,
+                                      ctypes.c_int]
+    for f in ("jzo_knn_bf", "jzo_knn_kd", "jzo_fof_bf", "jzo_fof_kd", "jzo_components_uf",
+              "jzo_components_bfs", "jzo_range_rows_bf"):
+        getattr(lib, f).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _pts(points) -> np.ndarray:
+    p = np.ascontiguousarray(points, dtype=np.float32)
+    if p.ndim != 2 or p.shape[1] != 3:
+        raise ValueError("points must have shape (n, 3)")
+    return p
+
+
+def _ptr(a, t):
+    return a.ctypes.data_as(t)
+
+
+def _knn(fn, points, k, rows, threads):
+    p = _pts(points)
+    n = p.shape[0]
+    if rows is None:
+        r = None
+        nr = n
+    else:
+        r = np.ascontiguousarray(rows, dtype=np.int64)
+        nr = r.shape[0]
+    idx = np.empty((nr, k), dtype=np.int32)
+    d2 = np.empty((nr, k), dtype=np.float32)
+    rc = fn(_ptr(p, _f32p), n, int(k), None if r is None else _ptr(r, _i64p), nr,
+            _ptr(idx, _i32p), _ptr(d2, _f32p), threads or default_threads())
+    if rc != 0:
+        raise RuntimeError("oracle kNN failed (%d)" % rc)
+    return idx, d2
+
+
+def knn_bf(points, k: int, rows=None, threads: int = 0):
+    """Brute-force kNN: (idx [r, k] int32, dist2 [r, k] float32) for all or given rows."""
+    return _knn(_load().jzo_knn_bf, points, k, rows, threads)
+
+
+def knn_kd(points, k: int, rows=None, threads: int = 0):
+    """Exact kd-tree kNN; same output as :func:`knn_bf`."""
+    return _knn(_load().jzo_knn_kd, points, k, rows, threads)
+
+
+def _fof(fn, points, b, threads):
+    p = _pts(points)
+    lab = np.empty(p.shape[0], dtype=np.int32)
+    rc = fn(_ptr(p, _f32p), p.shape[0], float(np.float32(b)), _ptr(lab, _i32p),
+            threads or default_threads())
+    if rc != 0:
+        raise RuntimeError("oracle FoF failed (%d)" % rc)
+    return lab
+
+
+def fof_bf(points, b: float, threads: int = 0) -> np.ndarray:
+    """Brute-force FoF labels (min member index), int32 [n]."""
+    return _fof(_load().jzo_fof_bf, points, b, threads)
+
+
+def fof_kd(points, b: float, threads: int = 0) -> np.ndarray:
+    """Exact kd-tree FoF labels; same output as :func:`fof_bf`."""
+    return _fof(_load().jzo_fof_kd, points, b, threads)
+
+
+def _components(fn, n, edges):
+    e = np.ascontiguousarray(edges, dtype=np.int32).reshape(-1, 2)
+    lab = np.empty(n, dtype=np.int32)
+    rc = fn(n, _ptr(e, _i32p), e.shape[0], _ptr(lab, _i32p))
+    if rc != 0:
+        raise RuntimeError("oracle components failed (%d)" % rc)
+    return lab
+
+
+def components_uf(n: int, edges) -> np.ndarray:
+    return _components(_load().jzo_components_uf, n, edges)
+
+
+def components_bfs(n: int, edges) -> np.ndarray:
+    return _components(_load().jzo_components_bfs, n, edges)
+
+
+def range_rows_bf(points, b: float, rows, cap: int = 4096, threads: int = 0):
+    """Neighbours within b (inclusive) of the given rows, brute force.
+
+    Returns (counts [r] int64, neighbours [r, cap] int32); a row's first
+    ``min(count, cap)`` entries are its neighbour indices in ascending order.
+    """
+    p = _pts(points)
+    r = np.ascontiguousarray(rows, dtype=np.int64)
+    cnt = np.empty(r.shape[0], dtype=np.int64)
+    nbr = np.full((r.shape[0], cap), -1, dtype=np.int32)
+    rc = _load().jzo_range_rows_bf(_ptr(p, _f32p), p.shape[0], float(np.float32(b)),
+                                   _ptr(r, _i64p), r.shape[0], cap, _ptr(cnt, _i64p),
+                                   _ptr(nbr, _i32p), threads or default_threads())
+    if rc != 0:
+        raise RuntimeError("oracle range search failed (%d)" % rc)
+    return cnt, nbr
+
+
+def dist2_f32(p, q) -> np.ndarray:
+    """The fixed float32 distance expression, elementwise over broadcast rows."""
+    p = np.asarray(p, dtype=np.float32)
+    q = np.asarray(q, dtype=np.float32)
+    d = p - q
+    xx = d[..., 0] * d[..., 0]
+    yy = d[..., 1] * d[..., 1]
+    zz = d[..., 2] * d[..., 2]
+    return (xx + yy) + zz
+
+
+def near_tie_report(points, idx, margin: int = 4):
+    """FP64 cross-check of a kNN result (a report, not a gate).
+
+    For each row, the float32 top-k plus the next ``margin`` candidates (taken
+    from a float32 brute-force row of length k + margin) are re-ranked by the
+    exact float64 squared distance and index. Returns the number of rows whose
+    float64 order would differ from the float32 result in membership or order.
+    """
+    p = _pts(points)
+    idx = np.asarray(idx)
+    k = idx.shape[1]
+    ext, _ = knn_bf(p, k + margin)
+    p64 = p.astype(np.float64)
+    flips = 0
+    for i in range(p.shape[0]):
+        cand = ext[i][ext[i] >= 0]
+        d = ((p64[cand] - p64[i]) ** 2).sum(axis=1)
+        order = np.lexsort((cand, d))
+        want = cand[order][:k]
+        got = idx[i][idx[i] >= 0]
+        if want.shape != got.shape or not np.array_equal(want, got):
+            flips += 1
+    return flips

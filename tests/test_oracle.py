@@ -1,0 +1,346 @@
+"""Pins for the CPU oracle: checks against what the paper and the mathematics fix.
+
+None of these tests touch the GPU. Each pin is chosen so that a plausible
+mistake in the oracle (a dropped term, a wrong sign or index, a wrong tie-break,
+an exclusive instead of inclusive comparison) fails at least one of them.
+"""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse
+import scipy.sparse.csgraph
+
+import oracle
+from oracle import planes
+from paper_2604_05885_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- helpers
+
+def full_sort_knn(p, k):
+    """Second, independent code path of the kNN definition: sort all n pairs
+    (dist2, j) of every row lexicographically and keep the first k."""
+    n = p.shape[0]
+    d = oracle.dist2_f32(p[:, None, :], p[None, :, :])
+    idx = np.full((n, k), -1, dtype=np.int32)
+    d2 = np.full((n, k), np.inf, dtype=np.float32)
+    for i in range(n):
+        order = np.lexsort((np.arange(n), d[i]))[:k]
+        idx[i, :len(order)] = order
+        d2[i, :len(order)] = d[i, order]
+    return idx, d2
+
+
+def edges_bf(p, b):
+    b2 = np.float32(b) * np.float32(b)
+    d = oracle.dist2_f32(p[:, None, :], p[None, :, :])
+    i, j = np.nonzero(np.triu(d <= b2, 1))
+    return np.stack([i, j], axis=1).astype(np.int32)
+
+
+def scipy_labels(n, edges):
+    """Connected components by scipy; relabelled to the min member index."""
+    g = scipy.sparse.coo_matrix((np.ones(len(edges)), (edges[:, 0], edges[:, 1])) if len(edges)
+                                else ([], ([], [])), shape=(n, n))
+    _, comp = scipy.sparse.csgraph.connected_components(g, directed=False)
+    first = np.full(comp.max() + 1, n, dtype=np.int64)
+    np.minimum.at(first, comp, np.arange(n))
+    return first[comp].astype(np.int32)
+
+
+def point_sets(seed, n):
+    rng = np.random.default_rng(seed)
+    yield "uniform", inputs.uniform(n, seed)
+    yield "clustered", inputs.clustered(n, max(1, n // 64), seed)
+    # duplicates and exact ties: points on a coarse grid, with repeats
+    g = rng.integers(0, 4, size=(n, 3)).astype(np.float32) * np.float32(0.25)
+    yield "coarse-grid-dups", g
+
+
+# ---------------------------------------------------------------- P1: kNN brute force vs full sort
+
+@pytest.mark.parametrize("seed", range(6))
+def test_knn_bf_matches_full_sort(seed):
+    for name, p in point_sets(seed, 200):
+        for k in (1, 5, 16, 32):
+            i1, d1 = oracle.knn_bf(p, k)
+            i2, d2 = full_sort_knn(p, k)
+            assert np.array_equal(i1, i2), (name, k)
+            assert np.array_equal(d1.view(np.uint32), d2.view(np.uint32)), (name, k)
+
+
+def test_knn_bf_k_larger_than_n_pads():
+    p = inputs.uniform(5, 3)
+    idx, d2 = oracle.knn_bf(p, 8)
+    assert np.all(idx[:, 5:] == -1) and np.all(np.isinf(d2[:, 5:]))
+    i2, _ = full_sort_knn(p, 5)
+    assert np.array_equal(idx[:, :5], i2)
+
+
+# ---------------------------------------------------------------- P2: lattice shells
+
+def test_knn_lattice_shells():
+    """Cubic lattice, spacing a = 2**-4: dist2 is (integer) * 2**-8 exactly, so the
+    neighbour shells of an interior point are known in closed form: 1 (self),
+    6 at a^2, 12 at 2a^2, 8 at 3a^2, with ties ordered by index."""
+    m = 9
+    p = inputs.lattice(m)
+    a2 = 2.0 ** -8
+
+    def index(i, j, l):
+        return (i * m + j) * m + l
+
+    centre = (4, 4, 4)
+    shells = {}
+    for di, dj, dl in itertools.product(range(-4, 5), repeat=3):
+        r2 = di * di + dj * dj + dl * dl
+        shells.setdefault(r2, []).append(index(centre[0] + di, centre[1] + dj, centre[2] + dl))
+    assert [len(shells[r]) for r in (0, 1, 2, 3)] == [1, 6, 12, 8]
+    row = index(*centre)
+    for k in (7, 19, 27):
+        idx, d2 = oracle.knn_bf(p, k, rows=[row])
+        want, want_d = [], []
+        for r2 in sorted(shells):
+            for j in sorted(shells[r2]):
+                want.append(j)
+                want_d.append(r2 * a2)
+        assert idx[0].tolist() == want[:k]
+        assert d2[0].astype(np.float64).tolist() == want_d[:k]
+
+
+# ---------------------------------------------------------------- P3: FoF on lattices
+
+def test_fof_lattice_thresholds():
+    p = inputs.lattice(6)
+    n = p.shape[0]
+    a = 2.0 ** -4
+    assert np.all(oracle.fof_bf(p, a * 1.01) == 0)
+    assert np.array_equal(oracle.fof_bf(p, a * 0.99), np.arange(n))
+    # exactly the spacing: the comparison is inclusive, so one group
+    assert np.all(oracle.fof_bf(p, a) == 0)
+
+
+def test_fof_two_offset_lattices():
+    a = 2.0 ** -4
+    p1 = inputs.lattice(4)
+    p2 = inputs.lattice(4, offset=(10, 0, 0))
+    p = np.concatenate([p1, p2])
+    lab = oracle.fof_bf(p, a * 1.5)
+    assert np.all(lab[:64] == 0) and np.all(lab[64:] == 64)
+
+
+# ---------------------------------------------------------------- P4: components
+
+@pytest.mark.parametrize("seed", range(5))
+def test_union_find_vs_bfs_random_graphs(seed):
+    rng = np.random.default_rng(seed)
+    n = 500
+    m = int(rng.integers(0, 800))
+    e = rng.integers(0, n, size=(m, 2)).astype(np.int32)
+    u = oracle.components_uf(n, e)
+    b = oracle.components_bfs(n, e)
+    s = scipy_labels(n, e)
+    assert np.array_equal(u, b) and np.array_equal(u, s)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_fof_bf_vs_components_of_edge_list(seed):
+    for name, p in point_sets(seed, 300):
+        for alpha in (0.1, 0.2, 0.6):
+            b = inputs.linking_length(p.shape[0], alpha)
+            e = edges_bf(p, b)
+            lab = oracle.fof_bf(p, b)
+            assert np.array_equal(lab, scipy_labels(p.shape[0], e)), (name, alpha)
+            assert np.array_equal(lab, oracle.components_bfs(p.shape[0], e)), (name, alpha)
+
+
+# ---------------------------------------------------------------- P5: special cases
+
+def test_special_cases():
+    # N = 1
+    p = np.array([[0.5, 0.25, 0.125]], dtype=np.float32)
+    idx, d2 = oracle.knn_bf(p, 1)
+    assert idx.tolist() == [[0]] and d2.tolist() == [[0.0]]
+    assert oracle.fof_bf(p, 0.0).tolist() == [0]
+    # k = 1 gives self, unless a lower-index duplicate exists
+    q = np.array([[0.1, 0.2, 0.3], [0.4, 0.4, 0.4], [0.1, 0.2, 0.3]], dtype=np.float32)
+    idx, _ = oracle.knn_bf(q, 1)
+    assert idx[:, 0].tolist() == [0, 1, 0]
+    # all points identical: kNN gives the first k indices; FoF one group at b = 0
+    same = np.tile(np.array([[0.3, 0.6, 0.9]], dtype=np.float32), (50, 1))
+    idx, d2 = oracle.knn_bf(same, 8)
+    assert np.all(idx == np.arange(8)) and np.all(d2 == 0)
+    assert np.all(oracle.fof_bf(same, 0.0) == 0)
+    # k = N gives the full sorted row
+    r = inputs.uniform(40, 9)
+    idx, _ = oracle.knn_bf(r, 40)
+    assert all(sorted(row) == list(range(40)) for row in idx.tolist())
+
+
+def test_subnormal_distances_kept():
+    """Tiny separations give subnormal dist2; flushing them to zero would change
+    the order (and an FoF link at b = 0)."""
+    t = np.float32(2.0 ** -70)
+    q = np.array([[0.0, 0.0, 0.0], [t, 0.0, 0.0], [2 * t, 0.0, 0.0]], dtype=np.float32)
+    idx, d2 = oracle.knn_bf(q, 3)
+    assert d2[0, 1] == np.float32(t * t) and d2[0, 1] > 0  # 2**-140 is subnormal in f32
+    assert idx[0].tolist() == [0, 1, 2]
+    lab = oracle.fof_bf(q, 0.0)
+    assert lab.tolist() == [0, 1, 2]
+
+
+# ---------------------------------------------------------------- P6: invariants
+
+@pytest.mark.parametrize("seed", range(3))
+def test_invariants(seed):
+    p = inputs.clustered(400, 8, seed)
+    d = oracle.dist2_f32(p[:, None, :], p[None, :, :])
+    assert np.array_equal(d.view(np.uint32), d.T.view(np.uint32))
+    idx, d2 = oracle.knn_bf(p, 16)
+    for i in range(p.shape[0]):
+        assert len(set(idx[i].tolist())) == 16
+        key = list(zip(d2[i].tolist(), idx[i].tolist()))
+        assert key == sorted(key)
+        assert np.array_equal(d2[i], d[i, idx[i]])
+    lab = oracle.fof_bf(p, inputs.linking_length(400))
+    assert np.all(lab <= np.arange(400)) and np.array_equal(lab[lab], lab)
+
+
+# ---------------------------------------------------------------- P7: Fig. 3 worked example
+
+def test_fig3_worked_example():
+    with open(os.path.join(GOLDEN, "fig3_tree.json")) as f:
+        g = json.load(f)
+    pts = [[x] for x in g["x"]]
+    lv = planes.gap_levels(pts)
+    assert lv == g["lvl"]
+    assert planes.node_sizes(lv) == g["n"]
+    spl = planes.planes(lv, g["nmax"])
+    assert spl[0] == g["spl0"] and spl[1] == g["spl1"]
+
+
+def test_eq5_equals_key_bitlength():
+    """On integer coordinates, Eq. 5 equals the bit length of the XOR of the
+    interleaved keys (dimension 0 most significant in each triple)."""
+    rng = np.random.default_rng(11)
+    q = rng.integers(0, 2 ** 21, size=(4000, 3))
+    # also pairs that share long prefixes
+    q2 = q ^ rng.integers(0, 2 ** rng.integers(0, 22, size=(4000, 1)), size=(4000, 3))
+    k1 = planes.interleave(q)
+    k2 = planes.interleave(q2)
+    for a in range(4000):
+        want = planes.lvl_int(q[a], q2[a])
+        got = (int(k1[a]) ^ int(k2[a])).bit_length()
+        assert got == (want if want >= 0 else 0)
+
+
+def test_planes_invariants_random():
+    """Each plane partitions the points; every node has at most N_max^(p) points
+    (it is a Morton cell or a single point); planes nest."""
+    rng = np.random.default_rng(5)
+    for trial in range(20):
+        n = int(rng.integers(1, 400))
+        p = inputs.clustered(n, 3, seed=100 + trial)
+        keys = planes.interleave(planes.quantize(p))
+        order = np.argsort(keys, kind="stable")
+        lv = planes.key_gap_levels(keys[order])
+        nmax = [4, 16, 64]
+        spl = planes.planes(list(lv), nmax)
+        gaps = spl[0]
+        assert gaps[0] == 0 and gaps[-1] == n
+        assert all(b - a <= nmax[0] for a, b in zip(gaps, gaps[1:]))
+        for pl in range(1, len(nmax)):
+            gaps = [gaps[j] for j in spl[pl]]
+            assert gaps[0] == 0 and gaps[-1] == n
+            assert all(b - a <= nmax[pl] for a, b in zip(gaps, gaps[1:]))
+
+
+# ---------------------------------------------------------------- P10 / P11: equivariance
+
+def test_scale_equivariance():
+    p = inputs.clustered(300, 6, 21)
+    idx, d2 = oracle.knn_bf(p, 12)
+    idx2, d22 = oracle.knn_bf(p * np.float32(2), 12)
+    assert np.array_equal(idx, idx2) and np.array_equal(d22, d2 * np.float32(4))
+    b = inputs.linking_length(300)
+    assert np.array_equal(oracle.fof_bf(p, b), oracle.fof_bf(p * np.float32(2), 2 * b))
+
+
+def test_permutation_equivariance():
+    p = inputs.uniform(300, 22)  # continuous: no ties
+    perm = np.random.default_rng(1).permutation(300)
+    idx, d2 = oracle.knn_bf(p, 10)
+    idxp, d2p = oracle.knn_bf(p[perm], 10)
+    inv = np.argsort(perm)
+    assert np.array_equal(perm[idxp], idx[perm])
+    assert np.array_equal(d2p, d2[perm])
+    b = inputs.linking_length(300, 0.5)
+    lab = oracle.fof_bf(p, b)
+    labp = oracle.fof_bf(p[perm], b)
+    # same partition: i and j grouped together before iff grouped together after
+    same = lab[:, None] == lab[None, :]
+    samep = labp[inv][:, None] == labp[inv][None, :]
+    assert np.array_equal(same, samep)
+
+
+# ---------------------------------------------------------------- P12: kd-tree == brute force
+
+@pytest.mark.parametrize("seed", range(12))
+def test_kd_equals_bf(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(1, 3000))
+    for name, p in point_sets(seed, n):
+        for k in (1, 8, 16, 32):
+            i1, d1 = oracle.knn_bf(p, k)
+            i2, d2 = oracle.knn_kd(p, k)
+            assert np.array_equal(i1, i2), (name, n, k)
+            assert np.array_equal(d1.view(np.uint32), d2.view(np.uint32)), (name, n, k)
+        for alpha in (0.1, 0.2, 0.7):
+            b = inputs.linking_length(n, alpha)
+            assert np.array_equal(oracle.fof_bf(p, b), oracle.fof_kd(p, b)), (name, n, alpha)
+
+
+def test_kd_equals_bf_dense_clumps():
+    """Clumps far denser than the linking length exercise the whole-box paths."""
+    p = inputs.clustered(20000, 4, seed=77, sigma_range=(0.001, 0.004))
+    b = inputs.linking_length(20000, 0.2)
+    assert np.array_equal(oracle.fof_bf(p, b), oracle.fof_kd(p, b))
+    rows = np.random.default_rng(3).choice(20000, 500, replace=False)
+    i1, d1 = oracle.knn_bf(p, 16, rows=rows)
+    i2, d2 = oracle.knn_kd(p, 16, rows=rows)
+    assert np.array_equal(i1, i2) and np.array_equal(d1, d2)
+
+
+def test_range_rows_bf():
+    p = inputs.uniform(500, 4)
+    b = 0.1
+    cnt, nbr = oracle.range_rows_bf(p, b, [0, 7])
+    d = oracle.dist2_f32(p[[0, 7]][:, None, :], p[None, :, :])
+    for r in range(2):
+        want = np.nonzero(d[r] <= np.float32(b) * np.float32(b))[0]
+        assert cnt[r] == len(want) and np.array_equal(nbr[r, :cnt[r]], want)
+
+
+def test_near_tie_report_runs():
+    p = inputs.lattice(5)  # exact ties everywhere; f32 == f64 here
+    idx, _ = oracle.knn_bf(p, 7)
+    assert oracle.near_tie_report(p, idx) == 0
+
+
+# ---------------------------------------------------------------- generators
+
+def test_generators_deterministic_and_in_range():
+    a = inputs.clustered(5000, 16, 3)
+    b = inputs.clustered(5000, 16, 3)
+    assert np.array_equal(a, b) and a.dtype == np.float32 and a.flags.c_contiguous
+    assert a.min() >= 0 and a.max() < 1
+    u = inputs.uniform(1000, 3)
+    assert u.min() >= 0 and u.max() < 1
+    _, info = inputs.clustered(100000, 64, 5, return_info=True)
+    assert info["n_clumped"] == 60000 and info["max_clump"] > 600
+    assert inputs.linking_length(2 ** 24) == float(np.float32(0.2 * 2.0 ** -8))
