@@ -1,0 +1,175 @@
+/*
+ * jz.h -- C ABI of the MI355X (gfx950) library for exact k-nearest-neighbour
+ * search and friends-of-friends (FoF) clustering of 3-D float32 point sets.
+ *
+ * Method: arXiv 2604.05885 ("jz-tree"). Points are sorted along a Morton
+ * (z-order) curve (section "Z-order sort"); a fixed-depth hierarchy of tree
+ * planes is built from the gaps between consecutive sorted points (section
+ * "Plane based tree-hierarchy", Eq. 7-9); a dual tree walk moves node-pair
+ * interaction lists from the coarsest plane down to the leaves (Alg. 1-3,
+ * Eq. 14-16), and the leaf stage computes exact kNN (kNN section) or links FoF
+ * groups (FoF section, Eq. 18-19).
+ *
+ * Conventions for every call below:
+ *  - Point and output buffers are DEVICE pointers (e.g. a torch tensor's
+ *    data_ptr() on the current HIP device); `stream` is a hipStream_t (NULL =
+ *    the default stream). The caller owns them.
+ *  - Points are float32, row-major [n][3] (x, y, z), 4-byte aligned. They must
+ *    be finite.
+ *  - Distances are compared as squared distances with the fixed float32
+ *    expression dist2 = fl(fl(fl(dx*dx) + fl(dy*dy)) + fl(dz*dz)),
+ *    dx = fl(x_i - x_j), no fused multiply-add, subnormals kept. Results are
+ *    exact with respect to that expression.
+ *  - All calls in this header are synchronous: they return after their work
+ *    on `stream` has completed, so that errors (capacity, non-finite input)
+ *    can be reported.
+ *  - Errors are returned as jz_status; jz_last_error() gives a message
+ *    (thread-local, valid until the next call on the same thread).
+ *  - A tree may be used by one thread / stream at a time; distinct trees are
+ *    independent.
+ */
+#ifndef JZ_H
+#define JZ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define JZ_API __attribute__((visibility("default")))
+#else
+#define JZ_API
+#endif
+
+typedef enum jz_status {
+    JZ_OK = 0,
+    JZ_E_INVALID = 1,      /* bad argument (null pointer, n out of range, k < 1, b < 0 or NaN) */
+    JZ_E_NONFINITE = 2,    /* an input coordinate is NaN or infinite */
+    JZ_E_UNSUPPORTED = 3,  /* k > 32 */
+    JZ_E_CAPACITY = 4,     /* interaction list overflow with auto_regrow = 0 */
+    JZ_E_OOM = 5,          /* device allocation failed */
+    JZ_E_DEVICE = 6        /* a HIP runtime error */
+} jz_status;
+
+/* Optional device allocator. alloc returns NULL on failure; memory must be
+ * device memory on the current device, 256-byte aligned. free receives the
+ * pointer and the size that alloc was called with. Both may be called from
+ * inside any jz_* call. NULL allocator = the library's own caching pool over
+ * hipMalloc. */
+typedef struct jz_allocator {
+    void *ctx;
+    void *(*alloc)(void *ctx, size_t bytes, void *stream);
+    void (*free)(void *ctx, void *ptr, size_t bytes, void *stream);
+} jz_allocator;
+
+/* Build options (tree-plane hierarchy of the paper's section on the plane
+ * based hierarchy; defaults follow its Eq. 8-9 and Alg. 1). */
+typedef struct jz_build_opts {
+    int leaf_max;          /* N_max^(0): most points per leaf. Default 48, range [1, 64]. */
+    int coarsen;           /* c in N_max^(p) = N_max^(0) c^p. Default 8, range [2, 64]. */
+    int n_target;          /* stop adding planes when N / (N_max^(p)/2) < n_target. Default 1000. */
+    int ngr;               /* top nodes per super node (NGR of Alg. 1). Default 32, range [1, 64]. */
+    int key_bits;          /* Morton bits per dimension. Default 21, range [1, 21]. */
+    float list_per_node;   /* initial interaction-list capacity in entries per node. Default 96. */
+    int auto_regrow;       /* 1 (default): on list overflow grow and rerun; 0: return JZ_E_CAPACITY. */
+    int keep_keys;         /* 1: keep the sorted Morton keys for jz_tree_export. Default 0. */
+} jz_build_opts;
+
+/* Fill *o with the defaults above. */
+JZ_API void jz_default_opts(jz_build_opts *o);
+
+typedef struct jz_tree jz_tree;
+
+/* Sort the n points in z-order and build the tree planes (paper: section on
+ * z-order trees, Eq. 7-9). `points` is read only during this call; the tree
+ * keeps its own sorted copy. n in [0, 2^31 - 2]. opts/alloc may be NULL.
+ * On success *out owns device memory until jz_tree_free. Errors:
+ * JZ_E_INVALID, JZ_E_NONFINITE, JZ_E_OOM, JZ_E_DEVICE (*out is then NULL). */
+JZ_API jz_status jz_build(const float *points, int64_t n, void *stream, const jz_build_opts *opts,
+                   const jz_allocator *alloc, jz_tree **out);
+
+/* Exact k nearest neighbours of every point, self included (paper: kNN
+ * section, Alg. 1-3 and the LeafToLeaf kernel). Row i of idx[n][k] holds the
+ * input indices of the k points closest to point i (input order), ascending by
+ * (dist2, index); dist2[n][k] holds their squared distances. If k > n the row
+ * tail is idx = -1, dist2 = +inf. k in [1, 32] (k > 32: JZ_E_UNSUPPORTED).
+ * idx and dist2 are device buffers of n*k elements. */
+JZ_API jz_status jz_knn(jz_tree *t, int k, int32_t *idx, float *dist2, void *stream);
+
+/* Friends-of-friends groups (paper: FoF section, Eq. 18): connected
+ * components of the graph linking every pair with dist2 <= fl(b*b).
+ * label[n] (device, input order) receives, for each point, the smallest input
+ * index in its group. b must be finite and >= 0. */
+JZ_API jz_status jz_fof(jz_tree *t, float b, int32_t *label, void *stream);
+
+/* Release the tree and its device memory (NULL is ignored). */
+JZ_API void jz_tree_free(jz_tree *t);
+
+/* ---- batched solving: many independent point sets in one tree ----------
+ * (the paper motivates repeated evaluations, e.g. simulation-based inference,
+ * in its introduction). Set s holds points[offsets[s] .. offsets[s+1]) of the
+ * concatenated array; `offsets` is a HOST array of nsets + 1 non-decreasing
+ * values with offsets[0] = 0 and offsets[nsets] = n, nsets in [1, 65536].
+ * One sort and one set of kernel launches cover all sets; no node straddles
+ * two sets and sets never interact, so every set's result equals what
+ * jz_build + jz_knn / jz_fof give for that set alone.
+ * On a forest, jz_knn writes set-local neighbour indices (row i of set s is
+ * global row offsets[s] + i; entries are indices within set s), and jz_fof
+ * uses one linking length for all sets with set-local labels. */
+JZ_API jz_status jz_forest_build(const float *points, const int64_t *offsets, int nsets, void *stream,
+                          const jz_build_opts *opts, const jz_allocator *alloc, jz_tree **out);
+
+/* FoF on a forest with one linking length per set (b: HOST array of nsets
+ * finite values >= 0). label[n] is set-local (smallest index within the set). */
+JZ_API jz_status jz_forest_fof(jz_tree *t, const float *b, int32_t *label, void *stream);
+
+#define JZ_MAX_PLANES 16
+
+typedef struct jz_stats {
+    int64_t n;                       /* points */
+    int planes;                      /* number of tree planes P */
+    int64_t nodes[JZ_MAX_PLANES];    /* nodes per plane (plane 0 = leaves) */
+    int64_t super_nodes;             /* super nodes over the top plane */
+    /* last jz_knn / jz_fof call on this tree */
+    int64_t list_entries[JZ_MAX_PLANES + 1]; /* list entries produced per level (index p = plane p, P = super) */
+    int64_t leaf_pairs;              /* leaf-leaf interactions in the leaf list */
+    int64_t leaf_pairs_visited;      /* of those, visited before the early exit */
+    double evaluations;              /* point-pair distance evaluations in the leaf stage */
+    double leaf_ms;                  /* leaf-stage kernel time (ms), when profiling is on */
+    double total_ms;                 /* whole call, device time (ms), when profiling is on */
+    int reruns;                      /* capacity reruns in the last call */
+} jz_stats;
+
+/* Statistics of the tree and of its last kNN / FoF call. */
+JZ_API jz_status jz_tree_stats(const jz_tree *t, jz_stats *s);
+
+/* Turn device-time measurement of the leaf stage and of whole calls on (1) or
+ * off (0) for calls made by this thread. Off by default. */
+JZ_API void jz_set_profiling(int on);
+
+/* Copy tree internals to HOST buffers, for tests. Any pointer may be NULL.
+ * order[n]: input index of each z-sorted point; keys[n]: sorted Morton keys
+ * (only if built with keep_keys = 1, else JZ_E_INVALID); for plane p, spl
+ * receives nodes[p] + 1 entries: plane 0 point offsets, plane p > 0 indices
+ * into the plane p-1 node array. */
+JZ_API jz_status jz_tree_export(const jz_tree *t, int32_t *order, uint64_t *keys, int plane,
+                         int32_t *spl);
+
+/* Return the library's cached (currently unused) device memory to the
+ * runtime. Trees keep their own memory until jz_tree_free. */
+JZ_API void jz_release_cached(void);
+
+/* Thread-local message of the last error (empty string if none). */
+JZ_API const char *jz_last_error(void);
+
+/* ABI version of this header (1). */
+JZ_API int jz_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* JZ_H */

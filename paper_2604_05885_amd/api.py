@@ -1,0 +1,286 @@
+"""Python binding of the C ABI in ``include/jz.h`` (argument marshalling only).
+
+Every step of the method runs in the HIP library ``libjz.so``; this module
+passes torch tensor pointers and HIP streams to it. There is no fallback: if
+the library is missing or fails to load, the import raises.
+
+Functions keep the C names (``jz_build``, ``jz_knn``, ``jz_fof``, ...);
+:class:`Tree` wraps a tree handle with ``knn`` / ``fof`` methods.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libjz.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "jz.h")
+
+JZ_OK, JZ_E_INVALID, JZ_E_NONFINITE, JZ_E_UNSUPPORTED, JZ_E_CAPACITY, JZ_E_OOM, JZ_E_DEVICE = range(7)
+MAX_PLANES = 16
+
+
+class JzError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("jz status %d: %s" % (status, msg))
+        self.status = status
+
+
+class BuildOpts(ctypes.Structure):
+    _fields_ = [("leaf_max", ctypes.c_int), ("coarsen", ctypes.c_int), ("n_target", ctypes.c_int),
+                ("ngr", ctypes.c_int), ("key_bits", ctypes.c_int),
+                ("list_per_node", ctypes.c_float), ("auto_regrow", ctypes.c_int),
+                ("keep_keys", ctypes.c_int)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("planes", ctypes.c_int),
+                ("nodes", ctypes.c_int64 * MAX_PLANES), ("super_nodes", ctypes.c_int64),
+                ("list_entries", ctypes.c_int64 * (MAX_PLANES + 1)),
+                ("leaf_pairs", ctypes.c_int64), ("leaf_pairs_visited", ctypes.c_int64),
+                ("evaluations", ctypes.c_double), ("leaf_ms", ctypes.c_double),
+                ("total_ms", ctypes.c_double), ("reruns", ctypes.c_int)]
+
+    def as_dict(self) -> dict:
+        P = self.planes
+        return {"n": self.n, "planes": P, "nodes": list(self.nodes[:P]),
+                "super_nodes": self.super_nodes,
+                "list_entries": list(self.list_entries[:P]),
+                "leaf_pairs": self.leaf_pairs, "leaf_pairs_visited": self.leaf_pairs_visited,
+                "evaluations": self.evaluations, "leaf_ms": self.leaf_ms,
+                "total_ms": self.total_ms, "reruns": self.reruns}
+
+
+class Allocator(ctypes.Structure):
+    _fields_ = [("ctx", ctypes.c_void_p),
+                ("alloc", ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                           ctypes.c_void_p)),
+                ("free", ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                          ctypes.c_void_p))]
+
+
+_vp = ctypes.c_void_p
+_SIGS = {
+    "jz_default_opts": (None, [ctypes.POINTER(BuildOpts)]),
+    "jz_build": (ctypes.c_int, [_vp, ctypes.c_int64, _vp, ctypes.POINTER(BuildOpts),
+                                ctypes.POINTER(Allocator), ctypes.POINTER(_vp)]),
+    "jz_knn": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp]),
+    "jz_fof": (ctypes.c_int, [_vp, ctypes.c_float, _vp, _vp]),
+    "jz_tree_free": (None, [_vp]),
+    "jz_forest_build": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int, _vp,
+                                       ctypes.POINTER(BuildOpts), ctypes.POINTER(Allocator),
+                                       ctypes.POINTER(_vp)]),
+    "jz_forest_fof": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_float), _vp, _vp]),
+    "jz_tree_stats": (ctypes.c_int, [_vp, ctypes.POINTER(Stats)]),
+    "jz_set_profiling": (None, [ctypes.c_int]),
+    "jz_tree_export": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp]),
+    "jz_release_cached": (None, []),
+    "jz_last_error": (ctypes.c_char_p, []),
+    "jz_abi_version": (ctypes.c_int, []),
+}
+
+
+def header_functions(path: str = HEADER_PATH) -> list:
+    """Names of the functions ``include/jz.h`` declares (JZ_API lines)."""
+    with open(path) as f:
+        text = f.read()
+    return re.findall(r"^JZ_API[^(]*?\b(jz_\w+)\s*\(", text, flags=re.M)
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libjz.so is not built (%s); run __graft_entry__.build() or "
+                          "python paper_2604_05885_amd/build.py" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def _check(status: int):
+    if status != JZ_OK:
+        raise JzError(status, lib.jz_last_error().decode(errors="replace"))
+
+
+def default_opts(**kw) -> BuildOpts:
+    o = BuildOpts()
+    lib.jz_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError("unknown option %r" % k)
+        setattr(o, k, v)
+    return o
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _points(points):
+    import torch
+    if not isinstance(points, torch.Tensor) or not points.is_cuda:
+        raise TypeError("points must be a CUDA (HIP) torch tensor")
+    if points.dtype != torch.float32 or points.dim() != 2 or points.shape[1] != 3:
+        raise TypeError("points must be float32 with shape (n, 3)")
+    return points.contiguous()
+
+
+def jz_set_profiling(on: bool):
+    lib.jz_set_profiling(1 if on else 0)
+
+
+def jz_release_cached():
+    lib.jz_release_cached()
+
+
+class Tree:
+    """A built tree (owns device memory until :meth:`free`)."""
+
+    def __init__(self, handle: ctypes.c_void_p, n: int, nsets: int = 1, offsets=None):
+        self._h = handle
+        self.n = n
+        self.nsets = nsets
+        self.offsets = offsets
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise RuntimeError("tree already freed")
+        return self._h
+
+    def knn(self, k: int, idx=None, dist2=None, stream=None):
+        """(idx [n, k] int32, dist2 [n, k] float32) on the tree's device."""
+        import torch
+        dev = torch.device("cuda", torch.cuda.current_device())
+        if idx is None:
+            idx = torch.empty((self.n, k), dtype=torch.int32, device=dev)
+        if dist2 is None:
+            dist2 = torch.empty((self.n, k), dtype=torch.float32, device=dev)
+        if tuple(idx.shape) != (self.n, k) or tuple(dist2.shape) != (self.n, k) or \
+                not idx.is_contiguous() or not dist2.is_contiguous() or \
+                idx.dtype != torch.int32 or dist2.dtype != torch.float32:
+            raise TypeError("idx / dist2 must be contiguous int32 / float32 of shape (n, k)")
+        _check(lib.jz_knn(self.handle, int(k), ctypes.c_void_p(idx.data_ptr()),
+                          ctypes.c_void_p(dist2.data_ptr()), _stream(stream)))
+        return idx, dist2
+
+    def fof(self, b, label=None, stream=None):
+        """Group labels [n] int32 (smallest member index). ``b`` is a float, or
+        for a forest also a sequence of one linking length per set."""
+        import torch
+        dev = torch.device("cuda", torch.cuda.current_device())
+        if label is None:
+            label = torch.empty(self.n, dtype=torch.int32, device=dev)
+        if tuple(label.shape) != (self.n,) or label.dtype != torch.int32 or \
+                not label.is_contiguous():
+            raise TypeError("label must be a contiguous int32 tensor of shape (n,)")
+        if np.ndim(b) == 0:
+            _check(lib.jz_fof(self.handle, float(np.float32(b)),
+                              ctypes.c_void_p(label.data_ptr()), _stream(stream)))
+        else:
+            bb = np.ascontiguousarray(b, dtype=np.float32)
+            if bb.shape != (self.nsets,):
+                raise ValueError("need one linking length per set")
+            _check(lib.jz_forest_fof(self.handle, bb.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                     ctypes.c_void_p(label.data_ptr()), _stream(stream)))
+        return label
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(lib.jz_tree_stats(self.handle, ctypes.byref(s)))
+        return s.as_dict()
+
+    def export(self, plane=None, order=False, keys=False):
+        """Host copies of tree internals (for tests)."""
+        out = {}
+        o = np.empty(self.n, dtype=np.int32) if order else None
+        k = np.empty(self.n, dtype=np.uint64) if keys else None
+        spl = None
+        if plane is not None:
+            st = self.stats()
+            spl = np.empty(st["nodes"][plane] + 1, dtype=np.int32)
+        _check(lib.jz_tree_export(self.handle,
+                                  o.ctypes.data_as(ctypes.c_void_p) if o is not None else None,
+                                  k.ctypes.data_as(ctypes.c_void_p) if k is not None else None,
+                                  int(plane if plane is not None else 0),
+                                  spl.ctypes.data_as(ctypes.c_void_p) if spl is not None else None))
+        if order:
+            out["order"] = o
+        if keys:
+            out["keys"] = k
+        if spl is not None:
+            out["spl"] = spl
+        return out
+
+    def free(self):
+        if self._h:
+            lib.jz_tree_free(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.free()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def jz_build(points, opts: BuildOpts | None = None, stream=None) -> Tree:
+    """Sort and build the tree for a CUDA float32 (n, 3) tensor."""
+    p = _points(points)
+    h = ctypes.c_void_p()
+    _check(lib.jz_build(ctypes.c_void_p(p.data_ptr()), p.shape[0], _stream(stream),
+                        ctypes.byref(opts) if opts is not None else None, None, ctypes.byref(h)))
+    return Tree(h, p.shape[0])
+
+
+def jz_forest_build(points, offsets, opts: BuildOpts | None = None, stream=None) -> Tree:
+    """One tree over many independent sets; ``offsets`` is a host int array [B+1]."""
+    p = _points(points)
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    h = ctypes.c_void_p()
+    _check(lib.jz_forest_build(ctypes.c_void_p(p.data_ptr()),
+                               off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), len(off) - 1,
+                               _stream(stream), ctypes.byref(opts) if opts is not None else None,
+                               None, ctypes.byref(h)))
+    return Tree(h, p.shape[0], len(off) - 1, off)
+
+
+def jz_knn(tree: Tree, k: int, stream=None):
+    return tree.knn(k, stream=stream)
+
+
+def jz_fof(tree: Tree, b, stream=None):
+    return tree.fof(b, stream=stream)
+
+
+def jz_tree_free(tree: Tree):
+    tree.free()
+
+
+def knn(points, k: int, opts: BuildOpts | None = None):
+    """Build + kNN in one call; returns (idx, dist2)."""
+    with jz_build(points, opts) as t:
+        return t.knn(k)
+
+
+def fof(points, b: float, opts: BuildOpts | None = None):
+    """Build + FoF in one call; returns labels."""
+    with jz_build(points, opts) as t:
+        return t.fof(b)

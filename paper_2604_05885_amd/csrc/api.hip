@@ -1,0 +1,353 @@
+// The C ABI (include/jz.h): argument checks, error reporting, the caching
+// device pool, and tree lifetime. The pipelines live in build.hip, knn.hip
+// and fof.hip.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <unordered_map>
+#include <vector>
+
+#include "jz_internal.h"
+
+// ---------------------------------------------------------------------------
+// errors and per-thread settings
+
+static thread_local std::string g_err;
+static thread_local bool g_prof = false;
+
+jz_status jz_fail(jz_status code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+jz_status jz_hip_fail(hipError_t e, const char *what, const char *file, int line) {
+    (void)hipGetLastError();
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+        return jz_fail(JZ_E_OOM, "%s: %s (%s:%d)", what, hipGetErrorString(e), file, line);
+    return jz_fail(JZ_E_DEVICE, "%s: %s (%s:%d)", what, hipGetErrorString(e), file, line);
+}
+
+bool jz_profiling() { return g_prof; }
+
+// ---------------------------------------------------------------------------
+// Caching device pool. Freed blocks keep an event recorded on the stream that
+// last used them; a block is handed to a different stream only after that
+// event has completed, so stream order protects every reuse.
+
+namespace {
+
+struct Block {
+    void *p;
+    size_t bytes;
+    hipStream_t s;
+    hipEvent_t ev;
+};
+
+struct Pool {
+    std::mutex m;
+    std::multimap<size_t, Block> free;
+    std::unordered_map<void *, size_t> live;
+};
+
+Pool &pool(int dev) {
+    static Pool pools[64];
+    return pools[dev & 63];
+}
+
+size_t round_size(size_t b) {
+    if (b >= (1u << 20)) return (b + (2u << 20) - 1) & ~(size_t)((2u << 20) - 1);
+    size_t r = 256;
+    while (r < b) r <<= 1;
+    return r;
+}
+
+void release_all(Pool &P) {
+    for (auto &kv : P.free) {
+        if (kv.second.ev) {
+            (void)hipEventSynchronize(kv.second.ev);
+            (void)hipEventDestroy(kv.second.ev);
+        }
+        (void)hipFree(kv.second.p);
+    }
+    P.free.clear();
+}
+
+}  // namespace
+
+void *dev_alloc(const AllocCtx &a, size_t bytes, hipStream_t s) {
+    if (a.user) return a.ua.alloc(a.ua.ctx, bytes, (void *)s);
+    Pool &P = pool(a.device);
+    const size_t want = round_size(bytes);
+    Block blk{};
+    bool found = false;
+    {
+        std::lock_guard<std::mutex> lk(P.m);
+        auto it = P.free.lower_bound(want);
+        if (it != P.free.end() && it->first <= 2 * want) {
+            blk = it->second;
+            P.free.erase(it);
+            found = true;
+        }
+    }
+    if (found) {
+        if (blk.ev) {
+            if (blk.s != s) (void)hipEventSynchronize(blk.ev);
+            (void)hipEventDestroy(blk.ev);
+        }
+        std::lock_guard<std::mutex> lk(P.m);
+        P.live[blk.p] = blk.bytes;
+        return blk.p;
+    }
+    void *p = nullptr;
+    if (hipMalloc(&p, want) != hipSuccess) {
+        (void)hipGetLastError();
+        std::lock_guard<std::mutex> lk(P.m);
+        release_all(P);
+        if (hipMalloc(&p, want) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+    }
+    std::lock_guard<std::mutex> lk(P.m);
+    P.live[p] = want;
+    return p;
+}
+
+void dev_free(const AllocCtx &a, void *p, size_t bytes, hipStream_t s) {
+    if (!p) return;
+    if (a.user) {
+        a.ua.free(a.ua.ctx, p, bytes, (void *)s);
+        return;
+    }
+    Pool &P = pool(a.device);
+    hipEvent_t ev = nullptr;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess) {
+        if (hipEventRecord(ev, s) != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipStreamSynchronize(s);
+            (void)hipEventDestroy(ev);
+            ev = nullptr;
+        }
+    } else {
+        (void)hipGetLastError();
+        (void)hipStreamSynchronize(s);
+        ev = nullptr;
+    }
+    std::lock_guard<std::mutex> lk(P.m);
+    auto it = P.live.find(p);
+    const size_t real = it != P.live.end() ? it->second : round_size(bytes);
+    if (it != P.live.end()) P.live.erase(it);
+    P.free.emplace(real, Block{p, real, s, ev});
+}
+
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+        else if (prev == dev) prev = -1;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+jz_status check_opts(const jz_build_opts &o) {
+    if (o.leaf_max < 1 || o.leaf_max > 64) return jz_fail(JZ_E_INVALID, "leaf_max must be in [1, 64]");
+    if (o.coarsen < 2 || o.coarsen > 64) return jz_fail(JZ_E_INVALID, "coarsen must be in [2, 64]");
+    if (o.n_target < 1) return jz_fail(JZ_E_INVALID, "n_target must be >= 1");
+    if (o.ngr < 1 || o.ngr > 64) return jz_fail(JZ_E_INVALID, "ngr must be in [1, 64]");
+    if (o.key_bits < 1 || o.key_bits > 21) return jz_fail(JZ_E_INVALID, "key_bits must be in [1, 21]");
+    if (!(o.list_per_node >= 1.0f) || !std::isfinite(o.list_per_node))
+        return jz_fail(JZ_E_INVALID, "list_per_node must be finite and >= 1");
+    return JZ_OK;
+}
+
+jz_status make_tree(const float *points, const int64_t *offsets, int nsets, int64_t n,
+                    void *stream, const jz_build_opts *opts, const jz_allocator *alloc,
+                    jz_tree **out) {
+    if (!out) return jz_fail(JZ_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (n < 0 || n > (int64_t)INT32_MAX - 1) return jz_fail(JZ_E_INVALID, "n must be in [0, 2^31-2]");
+    if (n > 0 && !points) return jz_fail(JZ_E_INVALID, "points is NULL");
+    if (alloc && (!alloc->alloc || !alloc->free))
+        return jz_fail(JZ_E_INVALID, "allocator needs both alloc and free");
+    jz_build_opts o;
+    jz_default_opts(&o);
+    if (opts) o = *opts;
+    JZ_TRY(check_opts(o));
+    jz_tree *t = new (std::nothrow) jz_tree();
+    if (!t) return jz_fail(JZ_E_OOM, "host allocation failed");
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        delete t;
+        return jz_fail(JZ_E_DEVICE, "no HIP device");
+    }
+    t->ac.device = dev;
+    if (alloc) {
+        t->ac.user = true;
+        t->ac.ua = *alloc;
+    }
+    t->opts = o;
+    t->n = n;
+    t->nsets = nsets;
+    t->set_off.assign(offsets, offsets + nsets + 1);
+    int sb = 0;
+    while ((1 << sb) < nsets) ++sb;
+    t->set_bits = sb;
+    hipStream_t s = (hipStream_t)stream;
+    jz_status st = t->d_set_off.get(&t->ac, (nsets + 1) * sizeof(int64_t), s);
+    if (st == JZ_OK) {
+        hipError_t e = hipMemcpyAsync(t->d_set_off.p, t->set_off.data(), (nsets + 1) * sizeof(int64_t),
+                                      hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) st = jz_hip_fail(e, "hipMemcpyAsync(set offsets)", __FILE__, __LINE__);
+    }
+    if (st == JZ_OK) st = build_tree(t, points, s);
+    if (st != JZ_OK) {
+        (void)hipStreamSynchronize(s);
+        delete t;
+        return st;
+    }
+    t->st.n = n;
+    *out = t;
+    return JZ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void jz_default_opts(jz_build_opts *o) {
+    if (!o) return;
+    o->leaf_max = 48;
+    o->coarsen = 8;
+    o->n_target = 1000;
+    o->ngr = 32;
+    o->key_bits = 21;
+    o->list_per_node = 96.0f;
+    o->auto_regrow = 1;
+    o->keep_keys = 0;
+}
+
+jz_status jz_build(const float *points, int64_t n, void *stream, const jz_build_opts *opts,
+                   const jz_allocator *alloc, jz_tree **out) {
+    g_err.clear();
+    const int64_t off[2] = {0, n < 0 ? 0 : n};
+    return make_tree(points, off, 1, n, stream, opts, alloc, out);
+}
+
+jz_status jz_forest_build(const float *points, const int64_t *offsets, int nsets, void *stream,
+                          const jz_build_opts *opts, const jz_allocator *alloc, jz_tree **out) {
+    g_err.clear();
+    if (out) *out = nullptr;
+    if (!offsets) return jz_fail(JZ_E_INVALID, "offsets is NULL");
+    if (nsets < 1 || nsets > 65536) return jz_fail(JZ_E_INVALID, "nsets must be in [1, 65536]");
+    if (offsets[0] != 0) return jz_fail(JZ_E_INVALID, "offsets[0] must be 0");
+    for (int i = 0; i < nsets; ++i)
+        if (offsets[i + 1] < offsets[i]) return jz_fail(JZ_E_INVALID, "offsets must be non-decreasing");
+    return make_tree(points, offsets, nsets, offsets[nsets], stream, opts, alloc, out);
+}
+
+jz_status jz_knn(jz_tree *t, int k, int32_t *idx, float *dist2, void *stream) {
+    g_err.clear();
+    if (!t) return jz_fail(JZ_E_INVALID, "tree is NULL");
+    if (k < 1) return jz_fail(JZ_E_INVALID, "k must be >= 1");
+    if (k > 32) return jz_fail(JZ_E_UNSUPPORTED, "k > 32 is not supported");
+    if (t->n > 0 && (!idx || !dist2)) return jz_fail(JZ_E_INVALID, "output is NULL");
+    DeviceGuard g(t->ac.device);
+    return run_knn(t, k, idx, dist2, (hipStream_t)stream);
+}
+
+jz_status jz_fof(jz_tree *t, float b, int32_t *label, void *stream) {
+    g_err.clear();
+    if (!t) return jz_fail(JZ_E_INVALID, "tree is NULL");
+    if (!(b >= 0.0f) || !std::isfinite(b)) return jz_fail(JZ_E_INVALID, "b must be finite and >= 0");
+    if (t->n > 0 && !label) return jz_fail(JZ_E_INVALID, "label is NULL");
+    DeviceGuard g(t->ac.device);
+    std::vector<float> b2(t->nsets, b * b);
+    return run_fof(t, b2.data(), label, (hipStream_t)stream);
+}
+
+jz_status jz_forest_fof(jz_tree *t, const float *b, int32_t *label, void *stream) {
+    g_err.clear();
+    if (!t) return jz_fail(JZ_E_INVALID, "tree is NULL");
+    if (!b) return jz_fail(JZ_E_INVALID, "b is NULL");
+    std::vector<float> b2(t->nsets);
+    for (int i = 0; i < t->nsets; ++i) {
+        if (!(b[i] >= 0.0f) || !std::isfinite(b[i]))
+            return jz_fail(JZ_E_INVALID, "b[%d] must be finite and >= 0", i);
+        b2[i] = b[i] * b[i];
+    }
+    if (t->n > 0 && !label) return jz_fail(JZ_E_INVALID, "label is NULL");
+    DeviceGuard g(t->ac.device);
+    return run_fof(t, b2.data(), label, (hipStream_t)stream);
+}
+
+void jz_tree_free(jz_tree *t) {
+    if (!t) return;
+    DeviceGuard g(t->ac.device);
+    delete t;
+}
+
+jz_status jz_tree_stats(const jz_tree *t, jz_stats *s) {
+    if (!t || !s) return jz_fail(JZ_E_INVALID, "NULL argument");
+    *s = t->st;
+    return JZ_OK;
+}
+
+void jz_set_profiling(int on) { g_prof = on != 0; }
+
+jz_status jz_tree_export(const jz_tree *t, int32_t *order, uint64_t *keys, int plane,
+                         int32_t *spl) {
+    g_err.clear();
+    if (!t) return jz_fail(JZ_E_INVALID, "tree is NULL");
+    DeviceGuard g(t->ac.device);
+    const int64_t n = t->n;
+    if (order && n > 0) {
+        std::vector<float> tmp(4 * n);
+        JZ_HIP(hipMemcpy(tmp.data(), t->pts4.p, n * 4 * sizeof(float), hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < n; ++i) std::memcpy(order + i, &tmp[4 * i + 3], sizeof(int32_t));
+    }
+    if (keys && n > 0) {
+        if (!t->keys.p) return jz_fail(JZ_E_INVALID, "tree was built without keep_keys");
+        JZ_HIP(hipMemcpy(keys, t->keys.p, n * sizeof(uint64_t), hipMemcpyDeviceToHost));
+    }
+    if (spl) {
+        if (plane < 0 || plane >= t->P) return jz_fail(JZ_E_INVALID, "plane out of range");
+        JZ_HIP(hipMemcpy(spl, t->spl[plane].p, (t->L[plane] + 1) * sizeof(int32_t),
+                         hipMemcpyDeviceToHost));
+    }
+    return JZ_OK;
+}
+
+void jz_release_cached(void) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    Pool &P = pool(dev);
+    std::lock_guard<std::mutex> lk(P.m);
+    release_all(P);
+}
+
+const char *jz_last_error(void) { return g_err.c_str(); }
+
+int jz_abi_version(void) { return 1; }
+
+}  // extern "C"

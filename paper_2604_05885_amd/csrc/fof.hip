@@ -1,0 +1,393 @@
+// Friends-of-friends by the same dual walk (paper: FoF section, Eq. 18-19).
+//
+// Group state: a point-level union-find `uf` over z-order indices (root =
+// smallest z-index of its group, linking higher root to lower root by CAS) plus
+// one "whole" flag per node and plane: a whole node's points are known to be
+// connected. The paper's ParentToNode advection (Eq. 19) becomes:
+//   - a child of a whole parent is whole, and its first point is pointed at
+//     the parent's first point (never touched before, so a plain store);
+//   - a node whose own diagonal is within the linking length is whole.
+// Node pairs (pairs are unordered: the lists hold sources >= receiver):
+//   discard if d_low^2 > b^2, or both whole and already one group;
+//   link    if d_up^2 <= b^2 (all member pairs linked): union the first
+//           points and mark both whole (each is connected through the other);
+//   descend otherwise (emit the pair into the next plane's list).
+// Leaves: point pairs with dist2 <= b^2 are united; a final pass writes each
+// point's group label as the smallest input index of its group.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <vector>
+
+#include "jz_device.h"
+#include "jz_internal.h"
+
+namespace {
+
+__global__ void k_iota_n(int *__restrict__ a, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = (int)i;
+}
+
+__global__ void k_fill(int *__restrict__ a, int64_t n, int v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+
+__global__ void k_node_b2(const int *__restrict__ node_set, int64_t L,
+                          const float *__restrict__ b2_set, float *__restrict__ b2n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < L) b2n[i] = b2_set[node_set[i]];
+}
+
+// ParentToNode: one wave per parent, lanes over its children.
+__global__ __launch_bounds__(256) void k_fof_p2n(const int *__restrict__ par_spl,
+                                                 const Node *__restrict__ nodes, int n_par,
+                                                 const int *__restrict__ whole_par,
+                                                 int *__restrict__ whole, int *__restrict__ uf,
+                                                 float b2, const float *__restrict__ b2n) {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int P = xcd_block(blockIdx.x, gridDim.x) * 4 + w;
+    if (P >= n_par) return;
+    const int c0 = par_spl[P], c1 = par_spl[P + 1];
+    const int wp = whole_par ? whole_par[P] : 0;
+    const int first = nodes[c0].start;
+    for (int c = c0 + lane; c < c1; c += 64) {
+        const Node me = nodes[c];
+        const float bb = b2n ? b2n[c] : b2;
+        const int wc = (wp || box_up2(me, me) <= bb) ? 1 : 0;
+        whole[c] = wc;
+        if (wp && c != c0) uf[me.start] = first;
+    }
+}
+
+// whole leaves: every point points at the leaf's first point
+__global__ __launch_bounds__(256) void k_fof_l2p(const Node *__restrict__ leaves, int n_leaves,
+                                                 const int *__restrict__ whole,
+                                                 int *__restrict__ uf) {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int A = xcd_block(blockIdx.x, gridDim.x) * 4 + w;
+    if (A >= n_leaves || !whole[A]) return;
+    const Node a = leaves[A];
+    for (int i = a.start + 1 + lane; i < a.start + a.count; i += 64) uf[i] = a.start;
+}
+
+enum PairCase { kDiscard = 0, kLinked = 1, kDescend = 2 };
+
+__device__ __forceinline__ int fof_case(const Node &me, int c, const Node &o, int s, float bb,
+                                        int *whole, int *uf, bool do_link, float &lo) {
+    lo = box_low2(me, o);
+    if (lo > bb) return kDiscard;
+    if (ld_acq(whole + c) && ld_acq(whole + s) && uf_find(uf, me.start) == uf_find(uf, o.start))
+        return kDiscard;
+    if (box_up2(me, o) <= bb) {
+        if (do_link) {
+            uf_union(uf, me.start, o.start);
+            st_rel(whole + c, 1);
+            st_rel(whole + s, 1);
+        }
+        return kLinked;
+    }
+    return kDescend;
+}
+
+// Node walk step: one wave per receiving parent, lanes over its children.
+// Pass A links and counts the pairs to descend into; pass B re-evaluates and
+// writes them (the group state only merges between the passes, so pass B
+// emits a subset of what pass A counted; the segment length is what it wrote).
+__global__ __launch_bounds__(256) void k_fof_step(
+    const int2 *__restrict__ seg_in, const int2 *__restrict__ list_in,
+    const int *__restrict__ par_spl, const Node *__restrict__ nodes, int n_par, float b2,
+    const float *__restrict__ b2n, int *__restrict__ whole, int *__restrict__ uf,
+    int2 *__restrict__ seg_out, int2 *__restrict__ list_out,
+    unsigned long long *__restrict__ ctr, long long cap) {
+    __shared__ Node s_tile[4][64];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int P = xcd_block(blockIdx.x, gridDim.x) * 4 + w;
+    if (P >= n_par) return;
+    const int2 sg = seg_in[P];
+    const int2 *gl = list_in + sg.x;
+    const int len = sg.y;
+    const int c0 = par_spl[P], c1 = par_spl[P + 1];
+    Node *tile = s_tile[w];
+    for (int cb = c0; cb < c1; cb += 64) {
+        const int c = cb + lane;
+        const bool act = c < c1;
+        const Node me = nodes[act ? c : c0];
+        const float bb = b2n ? b2n[act ? c : c0] : b2;
+        int cnt = 0;
+        for (int t = 0; t < len; ++t) {
+            const int S = gl[t].x;
+            const int s0 = par_spl[S], s1 = par_spl[S + 1];
+            for (int sb = s0; sb < s1; sb += 64) {
+                const int ns = min(64, s1 - sb);
+                if (lane < ns) tile[lane] = nodes[sb + lane];
+                wave_lds_sync();
+                for (int j = 0; j < ns; ++j) {
+                    const int s = sb + j;
+                    if (!act || s < c) continue;
+                    float lo;
+                    if (fof_case(me, c, tile[j], s, bb, whole, uf, true, lo) == kDescend) ++cnt;
+                }
+                wave_lds_sync();
+            }
+        }
+        const int incl = wave_incl_scan(cnt);
+        const int total = __shfl(incl, 63, 64);
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(ctr, (unsigned long long)total);
+        base = __shfl(base, 0, 64);
+        const long long pos = (long long)base + (incl - cnt);
+        const bool ok = (long long)base + total <= cap;
+        if (!ok) {
+            if (act) seg_out[c] = make_int2(0, 0);
+            continue;
+        }
+        int emitted = 0;
+        for (int t = 0; t < len; ++t) {
+            const int S = gl[t].x;
+            const int s0 = par_spl[S], s1 = par_spl[S + 1];
+            for (int sb = s0; sb < s1; sb += 64) {
+                const int ns = min(64, s1 - sb);
+                if (lane < ns) tile[lane] = nodes[sb + lane];
+                wave_lds_sync();
+                for (int j = 0; j < ns; ++j) {
+                    const int s = sb + j;
+                    if (!act || s < c || emitted >= cnt) continue;
+                    float lo;
+                    if (fof_case(me, c, tile[j], s, bb, whole, uf, false, lo) == kDescend) {
+                        list_out[pos + emitted] = make_int2(s, __float_as_int(lo));
+                        ++emitted;
+                    }
+                }
+                wave_lds_sync();
+            }
+        }
+        if (act) seg_out[c] = make_int2((int)pos, emitted);
+    }
+}
+
+// Leaf stage: one wave per receiving leaf, lanes over its points. Roots are
+// cached (a lane's own root, and the source points' roots per tile): equal
+// cached roots mean the two points were already connected, since groups only
+// ever merge.
+__global__ __launch_bounds__(256) void k_leaf_fof(
+    const int2 *__restrict__ seg, const int2 *__restrict__ list, const Node *__restrict__ leaves,
+    const float4 *__restrict__ pts, int n_leaves, float b2, const float *__restrict__ b2n,
+    const int *__restrict__ whole, int *__restrict__ uf, unsigned long long *__restrict__ stats) {
+    __shared__ float4 s_tile[4][64];
+    __shared__ int s_root[4][64];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int A = xcd_block(blockIdx.x, gridDim.x) * 4 + w;
+    if (A >= n_leaves) return;
+    const Node a = leaves[A];
+    const bool act = lane < a.count;
+    const int my = a.start + (act ? lane : 0);
+    const float4 me = pts[my];
+    const float bb = b2n ? b2n[A] : b2;
+    const int wA = whole[A];
+    const int2 sg = seg[A];
+    const int2 *gl = list + sg.x;
+    const int len = sg.y;
+    float4 *tile = s_tile[w];
+    int *rootB = s_root[w];
+    int ra = act ? uf_find(uf, my) : -1;
+    unsigned evals = 0;
+    for (int t = 0; t < len; ++t) {
+        const int B = gl[t].x;
+        const Node b = leaves[B];
+        const int wB = whole[B];
+        if (wA && wB && uf_find(uf, a.start) == uf_find(uf, b.start)) continue;
+        // b.count <= 64 (leaf_max <= 64)
+        if (lane < b.count) {
+            tile[lane] = pts[b.start + lane];
+            rootB[lane] = wB ? -2 : uf_find(uf, b.start + lane);
+        }
+        const int rB = wB ? uf_find(uf, b.start) : -2;
+        wave_lds_sync();
+        for (int j = 0; j < b.count; ++j) {
+            const int sj = b.start + j;
+            bool link = false;
+            if (act && sj > my) {
+                const float4 s = tile[j];
+                ++evals;
+                if (dist2_pts(me.x, me.y, me.z, s.x, s.y, s.z) <= bb) {
+                    const int rj = wB ? rB : rootB[j];
+                    if (rj != ra) {
+                        uf_union(uf, my, sj);
+                        ra = uf_find(uf, my);
+                    }
+                    link = true;
+                }
+            }
+            // two whole leaves need a single link
+            if (wA && wB && __ballot(link)) break;
+        }
+        wave_lds_sync();
+    }
+    const int ev = wave_sum((int)evals);
+    if (lane == 0) atomicAdd(stats, (unsigned long long)ev);
+}
+
+// root of every point (read-only find: no other thread writes uf[i] now)
+__global__ void k_flatten_min(int *__restrict__ uf, const float4 *__restrict__ pts, int64_t n,
+                              int *__restrict__ minidx) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int x = (int)i;
+    int p = ld_acq(uf + x);
+    while (p != x) {
+        x = p;
+        p = ld_acq(uf + x);
+    }
+    uf[i] = x;
+    atomicMin(minidx + x, __float_as_int(pts[i].w));
+}
+
+__global__ void k_labels(const int *__restrict__ uf, const float4 *__restrict__ pts, int64_t n,
+                         const int *__restrict__ minidx, const int64_t *__restrict__ set_off,
+                         int nsets, int32_t *__restrict__ label) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int o = __float_as_int(pts[i].w);
+    int base = 0;
+    if (nsets > 1) {
+        int lo_s = 0, hi_s = nsets - 1;
+        while (lo_s < hi_s) {
+            const int m = (lo_s + hi_s + 1) >> 1;
+            if (set_off[m] <= o) lo_s = m; else hi_s = m - 1;
+        }
+        base = (int)set_off[lo_s];
+    }
+    label[o] = minidx[uf[i]] - base;
+}
+
+}  // namespace
+
+jz_status run_fof(jz_tree *t, const float *b2_set_host, int32_t *label, hipStream_t s) {
+    const AllocCtx *ac = &t->ac;
+    const int P = t->P;
+    const int64_t n = t->n;
+    for (int p = 0; p <= JZ_MAX_PLANES; ++p) t->st.list_entries[p] = 0;
+    t->st.leaf_pairs = t->st.leaf_pairs_visited = 0;
+    t->st.evaluations = 0;
+    t->st.leaf_ms = t->st.total_ms = 0;
+    t->st.reruns = 0;
+    if (n == 0) return JZ_OK;
+
+    const bool sets = t->nsets > 1;
+    const float b2 = b2_set_host[0];
+    DBuf d_ctr, d_uf, d_min, d_b2set;
+    JZ_TRY(d_ctr.get(ac, (JZ_MAX_PLANES + 4) * sizeof(unsigned long long), s));
+    JZ_TRY(d_uf.get(ac, n * sizeof(int), s));
+    JZ_TRY(d_min.get(ac, n * sizeof(int), s));
+    unsigned long long *ctr = d_ctr.as<unsigned long long>();
+    DBuf whole[JZ_MAX_PLANES], b2n[JZ_MAX_PLANES];
+    int64_t maxL = 0;
+    for (int p = 0; p < P; ++p) {
+        JZ_TRY(whole[p].get(ac, t->L[p] * sizeof(int), s));
+        if (t->cap[p] == 0) t->cap[p] = (int64_t)(t->opts.list_per_node * (double)t->L[p]) + 1024;
+        if (t->cap[p] > INT_MAX) t->cap[p] = INT_MAX;
+        maxL = std::max<int64_t>(maxL, t->L[p]);
+    }
+    if (sets) {
+        JZ_TRY(d_b2set.get(ac, t->nsets * sizeof(float), s));
+        JZ_HIP(hipMemcpyAsync(d_b2set.p, b2_set_host, t->nsets * sizeof(float),
+                              hipMemcpyHostToDevice, s));
+        for (int p = 0; p < P; ++p) {
+            JZ_TRY(b2n[p].get(ac, t->L[p] * sizeof(float), s));
+            k_node_b2<<<blocks_for(t->L[p], 256), 256, 0, s>>>(t->node_set[p].as<int>(), t->L[p],
+                                                               d_b2set.as<float>(),
+                                                               b2n[p].as<float>());
+        }
+    }
+    DBuf segA, segB, listA, listB;
+    JZ_TRY(segA.get(ac, maxL * sizeof(int2), s));
+    JZ_TRY(segB.get(ac, maxL * sizeof(int2), s));
+    EventSet ev(jz_profiling());
+
+    for (;;) {
+        int64_t capmax = 0;
+        for (int p = 0; p < P; ++p) capmax = std::max(capmax, t->cap[p]);
+        JZ_TRY(listA.ensure(ac, capmax * sizeof(int2), s));
+        JZ_TRY(listB.ensure(ac, capmax * sizeof(int2), s));
+        JZ_HIP(hipMemsetAsync(ctr, 0, d_ctr.bytes, s));
+        if (ev.on) JZ_HIP(hipEventRecord(ev[0], s));
+        k_iota_n<<<blocks_for(n, 256), 256, 0, s>>>(d_uf.as<int>(), n);
+        k_fill<<<blocks_for(n, 256), 256, 0, s>>>(d_min.as<int>(), n, INT_MAX);
+        const int2 *seg_in = t->fof_top_seg.as<int2>();
+        const int2 *list_in = t->fof_top_list.as<int2>();
+        const int *par_spl = t->super_spl.as<int>();
+        const int *whole_par = nullptr;
+        int64_t n_par = t->S;
+        DBuf *segs[2] = {&segA, &segB};
+        DBuf *lists[2] = {&listA, &listB};
+        int which = 0;
+        for (int p = P - 1; p >= 0; --p) {
+            const float *bn = sets ? b2n[p].as<float>() : nullptr;
+            k_fof_p2n<<<blocks_for(n_par, 4), 256, 0, s>>>(par_spl, t->nodes[p].as<Node>(),
+                                                           (int)n_par, whole_par,
+                                                           whole[p].as<int>(), d_uf.as<int>(), b2,
+                                                           bn);
+            int2 *seg_out = segs[which]->as<int2>();
+            int2 *list_out = lists[which]->as<int2>();
+            k_fof_step<<<blocks_for(n_par, 4), 256, 0, s>>>(
+                seg_in, list_in, par_spl, t->nodes[p].as<Node>(), (int)n_par, b2, bn,
+                whole[p].as<int>(), d_uf.as<int>(), seg_out, list_out, ctr + p, t->cap[p]);
+            seg_in = seg_out;
+            list_in = list_out;
+            par_spl = t->spl[p].as<int>();
+            whole_par = whole[p].as<int>();
+            n_par = t->L[p];
+            which ^= 1;
+        }
+        k_fof_l2p<<<blocks_for(t->L[0], 4), 256, 0, s>>>(t->nodes[0].as<Node>(), (int)t->L[0],
+                                                         whole[0].as<int>(), d_uf.as<int>());
+        JZ_HIP(hipGetLastError());
+        if (ev.on) JZ_HIP(hipEventRecord(ev[1], s));
+        k_leaf_fof<<<blocks_for(t->L[0], 4), 256, 0, s>>>(
+            seg_in, list_in, t->nodes[0].as<Node>(), t->pts4.as<float4>(), (int)t->L[0], b2,
+            sets ? b2n[0].as<float>() : nullptr, whole[0].as<int>(), d_uf.as<int>(),
+            ctr + JZ_MAX_PLANES);
+        if (ev.on) JZ_HIP(hipEventRecord(ev[2], s));
+        k_flatten_min<<<blocks_for(n, 256), 256, 0, s>>>(d_uf.as<int>(), t->pts4.as<float4>(), n,
+                                                          d_min.as<int>());
+        k_labels<<<blocks_for(n, 256), 256, 0, s>>>(d_uf.as<int>(), t->pts4.as<float4>(), n,
+                                                     d_min.as<int>(), t->d_set_off.as<int64_t>(),
+                                                     t->nsets, label);
+        JZ_HIP(hipGetLastError());
+        if (ev.on) JZ_HIP(hipEventRecord(ev[3], s));
+        unsigned long long hc[JZ_MAX_PLANES + 4];
+        JZ_HIP(hipMemcpyAsync(hc, ctr, sizeof(hc), hipMemcpyDeviceToHost, s));
+        JZ_HIP(hipStreamSynchronize(s));
+        bool overflow = false;
+        for (int p = 0; p < P; ++p) {
+            t->st.list_entries[p] = (int64_t)hc[p];
+            if ((int64_t)hc[p] > t->cap[p]) {
+                overflow = true;
+                if ((int64_t)hc[p] > INT_MAX)
+                    return jz_fail(JZ_E_CAPACITY, "FoF list at plane %d needs %llu entries "
+                                   "(more than 2^31-1)", p, (unsigned long long)hc[p]);
+                const int64_t want = (int64_t)((double)hc[p] * 1.25) + 1024;
+                t->cap[p] = want > INT_MAX ? INT_MAX : want;
+            }
+        }
+        if (overflow) {
+            if (!t->opts.auto_regrow)
+                return jz_fail(JZ_E_CAPACITY, "FoF interaction list overflow; raise list_per_node");
+            t->st.reruns++;
+            continue;
+        }
+        t->st.leaf_pairs = t->st.list_entries[0];
+        t->st.evaluations = (double)hc[JZ_MAX_PLANES];
+        if (ev.on) {
+            float ms = 0;
+            JZ_HIP(hipEventElapsedTime(&ms, ev[1], ev[2]));
+            t->st.leaf_ms = ms;
+            JZ_HIP(hipEventElapsedTime(&ms, ev[0], ev[3]));
+            t->st.total_ms = ms;
+        }
+        return JZ_OK;
+    }
+}

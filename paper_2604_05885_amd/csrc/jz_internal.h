@@ -1,0 +1,155 @@
+// Host-side internals shared by the library's translation units: the tree
+// object, device allocation, error reporting and the pipeline entry points.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/jz.h"
+
+struct Node;
+
+// ---------------------------------------------------------------------------
+// errors
+
+jz_status jz_fail(jz_status code, const char *fmt, ...);
+jz_status jz_hip_fail(hipError_t e, const char *what, const char *file, int line);
+
+#define JZ_HIP(call)                                                          \
+    do {                                                                      \
+        hipError_t _e = (call);                                               \
+        if (_e != hipSuccess) return jz_hip_fail(_e, #call, __FILE__, __LINE__); \
+    } while (0)
+
+#define JZ_TRY(call)                       \
+    do {                                   \
+        jz_status _s = (call);             \
+        if (_s != JZ_OK) return _s;        \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// device memory
+
+struct AllocCtx {
+    bool user = false;
+    jz_allocator ua{};
+    int device = 0;
+};
+
+void *dev_alloc(const AllocCtx &a, size_t bytes, hipStream_t s);
+void dev_free(const AllocCtx &a, void *p, size_t bytes, hipStream_t s);
+
+// A device buffer owned by a tree or by one call.
+struct DBuf {
+    const AllocCtx *ac = nullptr;
+    void *p = nullptr;
+    size_t bytes = 0;
+    hipStream_t s = nullptr;
+
+    DBuf() = default;
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    ~DBuf() { release(); }
+
+    jz_status get(const AllocCtx *a, size_t b, hipStream_t st) {
+        release();
+        ac = a;
+        s = st;
+        bytes = b;
+        if (b == 0) return JZ_OK;
+        p = dev_alloc(*a, b, st);
+        if (!p) {
+            bytes = 0;
+            return jz_fail(JZ_E_OOM, "device allocation of %zu bytes failed", b);
+        }
+        return JZ_OK;
+    }
+    // keep the buffer if it is already large enough
+    jz_status ensure(const AllocCtx *a, size_t b, hipStream_t st) {
+        if (p && bytes >= b) {
+            s = st;
+            return JZ_OK;
+        }
+        return get(a, b, st);
+    }
+    void release() {
+        if (p) dev_free(*ac, p, bytes, s);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <class T>
+    T *as() const {
+        return static_cast<T *>(p);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// the tree
+
+struct jz_tree {
+    AllocCtx ac;
+    jz_build_opts opts{};
+    int64_t n = 0;
+
+    // independent point sets sharing one tree (a single set for jz_build)
+    int nsets = 1;
+    std::vector<int64_t> set_off;  // host, nsets + 1
+    int set_bits = 0;              // key bits above the Morton bits that hold the set id
+    DBuf d_set_off;                // int64 [nsets + 1]
+
+    // sorted points: float4 (x, y, z, input index as int bits)
+    DBuf pts4;
+    DBuf keys;  // uint64 [n], only with keep_keys
+
+    int P = 0;                       // planes
+    int64_t L[JZ_MAX_PLANES] = {};   // nodes per plane
+    DBuf nodes[JZ_MAX_PLANES];       // Node [L_p]
+    DBuf spl[JZ_MAX_PLANES];         // int [L_p + 1]
+    DBuf leaf_base;                  // int [L_0]: first input index of the leaf's set (sets > 1)
+    DBuf node_set[JZ_MAX_PLANES];    // int [L_p]: set of each node (sets > 1)
+
+    // super nodes over the top plane (NGR grouping of Alg. 1)
+    int64_t S = 0;
+    DBuf super_spl;                  // int [S + 1] ranges into the top plane
+    std::vector<int> super_set;      // host: set of each super node
+    DBuf knn_top_seg, knn_top_list;  // dense super-node list (all pairs within a set)
+    DBuf fof_top_seg, fof_top_list;  // dense super-node list (pairs s <= t within a set)
+
+    // interaction-list capacity per level (entries), grown on overflow
+    int64_t cap[JZ_MAX_PLANES] = {};
+
+    jz_stats st{};
+};
+
+// pipelines (build.hip / knn.hip / fof.hip)
+jz_status build_tree(jz_tree *t, const float *points, hipStream_t s);
+jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s);
+jz_status run_fof(jz_tree *t, const float *b2_set_host, int32_t *label, hipStream_t s);
+
+bool jz_profiling();
+
+// hipEvents for optional device timing; created only when profiling is on
+struct EventSet {
+    bool on = false;
+    hipEvent_t e[4] = {};
+    explicit EventSet(bool want) {
+        if (!want) return;
+        on = true;
+        for (auto &x : e)
+            if (hipEventCreate(&x) != hipSuccess) on = false;
+    }
+    ~EventSet() {
+        for (auto &x : e)
+            if (x) (void)hipEventDestroy(x);
+    }
+    hipEvent_t operator[](int i) const { return e[i]; }
+};
+
+// launch helpers
+inline unsigned blocks_for(int64_t items, int per_block) {
+    int64_t b = (items + per_block - 1) / per_block;
+    return (unsigned)(b < 1 ? 1 : b);
+}

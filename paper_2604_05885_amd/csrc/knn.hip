@@ -1,0 +1,412 @@
+// Exact kNN by a dual walk over the tree planes (paper: kNN section, Alg. 1-3,
+// Eq. 14-16, and the implementation-details subsection on r_low ordering).
+//
+// Level step (one wave per receiving parent; lanes = its children):
+//   pass 1  FindRmax: register heap of (d_up^2, count); R = smallest radius
+//           whose cumulative count reaches k (Alg. 3)
+//   pass 2  count children pairs with d_low^2 <= R
+//   pass 3  insert them (with r_low = d_low^2) into the next list, at an
+//           offset reserved with one atomic per wave
+// The paper's separate Count / prefix-sum / Insert launches become one kernel.
+// Each receiver's source list is staged in LDS and sorted by r_low so that the
+// early exit "r_low > max over lanes of R" can drop the rest of the list.
+//
+// Leaf stage (one wave per receiving leaf; lanes = its query points): source
+// leaves in r_low order, each staged in LDS as float4 (x, y, z, index); every
+// lane keeps its top-k as packed (dist2 bits, index) u64 keys in registers.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <vector>
+
+#include "jz_device.h"
+#include "jz_internal.h"
+
+namespace {
+
+constexpr int LCAP = 256;  // list entries staged (and sorted) in LDS per wave
+constexpr uint64_t PAD_KEY = (0x7f800000ull << 32) | 0xffffffffull;  // (+inf, no index)
+
+__device__ __forceinline__ uint64_t list_key(int2 e) {
+    return ((uint64_t)(uint32_t)e.y << 32) | (uint32_t)e.x;  // r_low >= 0: bits order as floats
+}
+
+// Stage a receiver's list in LDS and sort it ascending by (r_low, source).
+__device__ void stage_sorted(const int2 *__restrict__ src, int len, uint64_t *L) {
+    int M = 1;
+    while (M < len) M <<= 1;
+    for (int i = lane_id(); i < M; i += 64) L[i] = i < len ? list_key(src[i]) : ~0ull;
+    wave_lds_sync();
+    for (int k = 2; k <= M; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = lane_id(); i < (M >> 1); i += 64) {
+                const int a = ((i & ~(j - 1)) << 1) | (i & (j - 1));
+                const int b = a + j;
+                const uint64_t x = L[a], y = L[b];
+                const bool up = (a & k) == 0;
+                if ((x > y) == up) {
+                    L[a] = y;
+                    L[b] = x;
+                }
+            }
+            wave_lds_sync();
+        }
+    }
+}
+
+__device__ __forceinline__ void list_entry(bool staged, const uint64_t *L, const int2 *g, int t,
+                                           int &src, float &rl) {
+    if (staged) {
+        const uint64_t e = L[t];
+        src = (int)(uint32_t)e;
+        rl = __uint_as_float((uint32_t)(e >> 32));
+    } else {
+        const int2 e = g[t];
+        src = e.x;
+        rl = __int_as_float(e.y);
+    }
+}
+
+// Register heap of (radius, count), sorted by radius. Inserting pushes the
+// largest entry out; its count is merged into the last slot at its (larger)
+// radius, which keeps "at least C points within radius r" true for every
+// prefix.
+template <int NR>
+__device__ __forceinline__ void heap_insert(float (&hr)[NR], int (&hc)[NR], float r, int c) {
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        const bool sw = r < hr[i];
+        const float tr = sw ? hr[i] : r;
+        const int tc = sw ? hc[i] : c;
+        hr[i] = sw ? r : hr[i];
+        hc[i] = sw ? c : hc[i];
+        r = tr;
+        c = tc;
+    }
+    if (c > 0) {
+        hr[NR - 1] = r;
+        hc[NR - 1] += c;
+    }
+}
+
+// smallest radius whose cumulative count reaches k (+inf if the total is < k)
+template <int NR>
+__device__ __forceinline__ float radius_of_count(const float (&hr)[NR], const int (&hc)[NR],
+                                                 int k) {
+    int acc = 0;
+    float R = INFINITY;
+    bool found = false;
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        acc += hc[i];
+        if (!found && acc >= k) {
+            R = hr[i];
+            found = true;
+        }
+    }
+    return R;
+}
+
+constexpr int NR_HEAP = 8;
+
+__global__ __launch_bounds__(256) void k_knn_step(
+    const int2 *__restrict__ seg_in, const int2 *__restrict__ list_in,
+    const int *__restrict__ par_spl, const Node *__restrict__ nodes, int n_par, int k,
+    int2 *__restrict__ seg_out, int2 *__restrict__ list_out,
+    unsigned long long *__restrict__ ctr, long long cap) {
+    __shared__ uint64_t s_list[4][LCAP];
+    __shared__ Node s_tile[4][64];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int P = xcd_block(blockIdx.x, gridDim.x) * 4 + w;
+    if (P >= n_par) return;
+    const int2 sg = seg_in[P];
+    const int2 *gl = list_in + sg.x;
+    const int len = sg.y;
+    const int c0 = par_spl[P], c1 = par_spl[P + 1];
+    uint64_t *L = s_list[w];
+    Node *tile = s_tile[w];
+    const bool staged = len <= LCAP;
+    if (staged) stage_sorted(gl, len, L);
+
+    for (int cb = c0; cb < c1; cb += 64) {
+        const int c = cb + lane;
+        const bool act = c < c1;
+        const Node me = nodes[act ? c : c0];
+        float hr[NR_HEAP];
+        int hc[NR_HEAP];
+#pragma unroll
+        for (int i = 0; i < NR_HEAP; ++i) {
+            hr[i] = INFINITY;
+            hc[i] = 0;
+        }
+        float R = INFINITY;
+        // pass 1: FindRmax
+        for (int t = 0; t < len; ++t) {
+            int src;
+            float rl;
+            list_entry(staged, L, gl, t, src, rl);
+            if (staged && rl > wave_max(act ? R : -INFINITY)) break;
+            const int s0 = par_spl[src], s1 = par_spl[src + 1];
+            for (int sb = s0; sb < s1; sb += 64) {
+                const int ns = min(64, s1 - sb);
+                if (lane < ns) tile[lane] = nodes[sb + lane];
+                wave_lds_sync();
+                for (int j = 0; j < ns; ++j) {
+                    const Node o = tile[j];
+                    const float r = box_up2(me, o);
+                    if (act && r < R) {
+                        heap_insert<NR_HEAP>(hr, hc, r, o.count);
+                        R = radius_of_count<NR_HEAP>(hr, hc, k);
+                    }
+                }
+                wave_lds_sync();
+            }
+        }
+        const float Rw = wave_max(act ? R : -INFINITY);
+        // pass 2: count
+        int cnt = 0;
+        for (int t = 0; t < len; ++t) {
+            int src;
+            float rl;
+            list_entry(staged, L, gl, t, src, rl);
+            if (staged && rl > Rw) break;
+            const int s0 = par_spl[src], s1 = par_spl[src + 1];
+            for (int sb = s0; sb < s1; sb += 64) {
+                const int ns = min(64, s1 - sb);
+                if (lane < ns) tile[lane] = nodes[sb + lane];
+                wave_lds_sync();
+                for (int j = 0; j < ns; ++j) cnt += (act && box_low2(me, tile[j]) <= R) ? 1 : 0;
+                wave_lds_sync();
+            }
+        }
+        // reserve
+        const int incl = wave_incl_scan(cnt);
+        const int total = __shfl(incl, 63, 64);
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(ctr, (unsigned long long)total);
+        base = __shfl(base, 0, 64);
+        const long long pos = (long long)base + (incl - cnt);
+        const bool ok = (long long)base + total <= cap;
+        if (act) seg_out[c] = ok ? make_int2((int)pos, cnt) : make_int2(0, 0);
+        if (!ok) continue;
+        // pass 3: insert
+        long long wp = pos;
+        for (int t = 0; t < len; ++t) {
+            int src;
+            float rl;
+            list_entry(staged, L, gl, t, src, rl);
+            if (staged && rl > Rw) break;
+            const int s0 = par_spl[src], s1 = par_spl[src + 1];
+            for (int sb = s0; sb < s1; sb += 64) {
+                const int ns = min(64, s1 - sb);
+                if (lane < ns) tile[lane] = nodes[sb + lane];
+                wave_lds_sync();
+                for (int j = 0; j < ns; ++j) {
+                    const float lo = box_low2(me, tile[j]);
+                    if (act && lo <= R) {
+                        list_out[wp] = make_int2(sb + j, __float_as_int(lo));
+                        ++wp;
+                    }
+                }
+                wave_lds_sync();
+            }
+        }
+    }
+}
+
+template <int K>
+__device__ __forceinline__ void topk_insert(uint64_t (&b)[K], uint64_t key) {
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const uint64_t lo = b[i] < key ? b[i] : key;
+        key = b[i] < key ? key : b[i];
+        b[i] = lo;
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void k_leaf_knn(
+    const int2 *__restrict__ seg, const int2 *__restrict__ list, const Node *__restrict__ leaves,
+    const float4 *__restrict__ pts, int n_leaves, const int *__restrict__ leaf_base,
+    int32_t *__restrict__ out_idx, float *__restrict__ out_d2,
+    unsigned long long *__restrict__ stats) {
+    __shared__ uint64_t s_list[4][LCAP];
+    __shared__ float4 s_tile[4][64];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int A = xcd_block(blockIdx.x, gridDim.x) * 4 + w;
+    if (A >= n_leaves) return;
+    const Node a = leaves[A];
+    const bool act = lane < a.count;
+    const float4 me = pts[a.start + (act ? lane : 0)];
+    const int2 sg = seg[A];
+    const int2 *gl = list + sg.x;
+    const int len = sg.y;
+    uint64_t *L = s_list[w];
+    float4 *tile = s_tile[w];
+    const bool staged = len <= LCAP;
+    if (staged) stage_sorted(gl, len, L);
+
+    uint64_t best[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) best[i] = PAD_KEY;
+    unsigned evals = 0, visited = 0;
+    for (int t = 0; t < len; ++t) {
+        int src;
+        float rl;
+        list_entry(staged, L, gl, t, src, rl);
+        const float kth = __uint_as_float((uint32_t)(best[K - 1] >> 32));
+        if (staged && rl > wave_max(act ? kth : -INFINITY)) break;
+        ++visited;
+        const Node b = leaves[src];
+        const int e1 = b.start + b.count;
+        for (int sb = b.start; sb < e1; sb += 64) {
+            const int ns = min(64, e1 - sb);
+            if (lane < ns) tile[lane] = pts[sb + lane];
+            wave_lds_sync();
+            for (int j = 0; j < ns; ++j) {
+                const float4 s = tile[j];
+                const float dd = dist2_pts(me.x, me.y, me.z, s.x, s.y, s.z);
+                const uint64_t key = ((uint64_t)__float_as_uint(dd) << 32) | (uint32_t)__float_as_int(s.w);
+                if (act && key < best[K - 1]) topk_insert<K>(best, key);
+            }
+            evals += act ? ns : 0;
+            wave_lds_sync();
+        }
+    }
+    if (act) {
+        const int64_t row = (int64_t)__float_as_int(me.w);
+        const int base = leaf_base ? leaf_base[A] : 0;
+        int32_t *oi = out_idx + row * K;
+        float *od = out_d2 + row * K;
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+            const uint64_t e = best[r];
+            const bool pad = e == PAD_KEY;
+            oi[r] = pad ? -1 : (int)(uint32_t)e - base;
+            od[r] = pad ? INFINITY : __uint_as_float((uint32_t)(e >> 32));
+        }
+    }
+    const int ev = wave_sum((int)evals);
+    if (lane == 0) {
+        atomicAdd(stats + 0, (unsigned long long)ev);
+        atomicAdd(stats + 1, (unsigned long long)visited);
+    }
+}
+
+typedef void (*leaf_fn)(const int2 *, const int2 *, const Node *, const float4 *, int, const int *,
+                        int32_t *, float *, unsigned long long *);
+
+template <int K>
+leaf_fn leaf_ptr() {
+    return k_leaf_knn<K>;
+}
+
+leaf_fn leaf_kernel(int k) {
+    static const leaf_fn table[33] = {
+        nullptr,       leaf_ptr<1>(),  leaf_ptr<2>(),  leaf_ptr<3>(),  leaf_ptr<4>(),
+        leaf_ptr<5>(), leaf_ptr<6>(),  leaf_ptr<7>(),  leaf_ptr<8>(),  leaf_ptr<9>(),
+        leaf_ptr<10>(), leaf_ptr<11>(), leaf_ptr<12>(), leaf_ptr<13>(), leaf_ptr<14>(),
+        leaf_ptr<15>(), leaf_ptr<16>(), leaf_ptr<17>(), leaf_ptr<18>(), leaf_ptr<19>(),
+        leaf_ptr<20>(), leaf_ptr<21>(), leaf_ptr<22>(), leaf_ptr<23>(), leaf_ptr<24>(),
+        leaf_ptr<25>(), leaf_ptr<26>(), leaf_ptr<27>(), leaf_ptr<28>(), leaf_ptr<29>(),
+        leaf_ptr<30>(), leaf_ptr<31>(), leaf_ptr<32>()};
+    return table[k];
+}
+
+}  // namespace
+
+jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s) {
+    const AllocCtx *ac = &t->ac;
+    const int P = t->P;
+    for (int p = 0; p <= JZ_MAX_PLANES; ++p) t->st.list_entries[p] = 0;
+    t->st.leaf_pairs = t->st.leaf_pairs_visited = 0;
+    t->st.evaluations = 0;
+    t->st.leaf_ms = t->st.total_ms = 0;
+    t->st.reruns = 0;
+    if (t->n == 0) return JZ_OK;
+
+    DBuf d_ctr;
+    JZ_TRY(d_ctr.get(ac, (JZ_MAX_PLANES + 4) * sizeof(unsigned long long), s));
+    unsigned long long *ctr = d_ctr.as<unsigned long long>();
+    int64_t maxL = 0;
+    for (int p = 0; p < P; ++p) {
+        if (t->cap[p] == 0) t->cap[p] = (int64_t)(t->opts.list_per_node * (double)t->L[p]) + 1024;
+        if (t->cap[p] > INT_MAX) t->cap[p] = INT_MAX;
+        maxL = std::max<int64_t>(maxL, t->L[p]);
+    }
+    DBuf segA, segB, listA, listB;
+    JZ_TRY(segA.get(ac, maxL * sizeof(int2), s));
+    JZ_TRY(segB.get(ac, maxL * sizeof(int2), s));
+    EventSet ev(jz_profiling());
+    const bool prof = ev.on;
+
+    for (int attempt = 0;; ++attempt) {
+        int64_t capmax = 0;
+        for (int p = 0; p < P; ++p) capmax = std::max(capmax, t->cap[p]);
+        JZ_TRY(listA.ensure(ac, capmax * sizeof(int2), s));
+        JZ_TRY(listB.ensure(ac, capmax * sizeof(int2), s));
+        JZ_HIP(hipMemsetAsync(ctr, 0, d_ctr.bytes, s));
+        if (prof) JZ_HIP(hipEventRecord(ev[0], s));
+        const int2 *seg_in = t->knn_top_seg.as<int2>();
+        const int2 *list_in = t->knn_top_list.as<int2>();
+        const int *par_spl = t->super_spl.as<int>();
+        int64_t n_par = t->S;
+        DBuf *segs[2] = {&segA, &segB};
+        DBuf *lists[2] = {&listA, &listB};
+        int which = 0;
+        for (int p = P - 1; p >= 0; --p) {
+            int2 *seg_out = segs[which]->as<int2>();
+            int2 *list_out = lists[which]->as<int2>();
+            k_knn_step<<<blocks_for(n_par, 4), 256, 0, s>>>(seg_in, list_in, par_spl,
+                                                            t->nodes[p].as<Node>(), (int)n_par, k,
+                                                            seg_out, list_out, ctr + p, t->cap[p]);
+            seg_in = seg_out;
+            list_in = list_out;
+            par_spl = t->spl[p].as<int>();
+            n_par = t->L[p];
+            which ^= 1;
+        }
+        JZ_HIP(hipGetLastError());
+        if (prof) JZ_HIP(hipEventRecord(ev[1], s));
+        leaf_kernel(k)<<<blocks_for(t->L[0], 4), 256, 0, s>>>(
+            seg_in, list_in, t->nodes[0].as<Node>(), t->pts4.as<float4>(), (int)t->L[0],
+            t->nsets > 1 ? t->leaf_base.as<int>() : nullptr, idx, dist2, ctr + JZ_MAX_PLANES);
+        JZ_HIP(hipGetLastError());
+        if (prof) JZ_HIP(hipEventRecord(ev[2], s));
+        unsigned long long hc[JZ_MAX_PLANES + 4];
+        JZ_HIP(hipMemcpyAsync(hc, ctr, sizeof(hc), hipMemcpyDeviceToHost, s));
+        JZ_HIP(hipStreamSynchronize(s));
+        bool overflow = false;
+        for (int p = 0; p < P; ++p) {
+            t->st.list_entries[p] = (int64_t)hc[p];
+            if ((int64_t)hc[p] > t->cap[p]) {
+                overflow = true;
+                int64_t want = (int64_t)((double)hc[p] * 1.25) + 1024;
+                t->cap[p] = want > INT_MAX ? INT_MAX : want;
+                if ((int64_t)hc[p] > INT_MAX)
+                    return jz_fail(JZ_E_CAPACITY, "interaction list at plane %d needs %llu entries "
+                                   "(more than 2^31-1)", p, (unsigned long long)hc[p]);
+            }
+        }
+        if (overflow) {
+            if (!t->opts.auto_regrow)
+                return jz_fail(JZ_E_CAPACITY,
+                               "interaction list overflow; set list_per_node to at least %.1f",
+                               (double)t->cap[0] / (double)std::max<int64_t>(1, t->L[0]));
+            t->st.reruns++;
+            continue;
+        }
+        t->st.leaf_pairs = t->st.list_entries[0];
+        t->st.evaluations = (double)hc[JZ_MAX_PLANES];
+        t->st.leaf_pairs_visited = (int64_t)hc[JZ_MAX_PLANES + 1];
+        if (prof) {
+            float ms = 0;
+            JZ_HIP(hipEventElapsedTime(&ms, ev[1], ev[2]));
+            t->st.leaf_ms = ms;
+            JZ_HIP(hipEventElapsedTime(&ms, ev[0], ev[2]));
+            t->st.total_ms = ms;
+        }
+        return JZ_OK;
+    }
+}

@@ -1,0 +1,227 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+kNN indices and squared distances, and FoF labels, must match bit for bit
+(integer results: exact; the float32 distances come from the same fixed
+expression on both sides, so they are compared bitwise too).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import planes
+from paper_2604_05885_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def jz():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2604_05885_amd import api
+    return api
+
+
+def to_dev(p):
+    return torch.from_numpy(np.ascontiguousarray(p, dtype=np.float32)).cuda()
+
+
+def gpu_knn(jz, p, k, **opts):
+    with jz.jz_build(to_dev(p), jz.default_opts(**opts) if opts else None) as t:
+        idx, d2 = t.knn(k)
+        torch.cuda.synchronize()
+        return idx.cpu().numpy(), d2.cpu().numpy(), t.stats()
+
+
+def gpu_fof(jz, p, b, **opts):
+    with jz.jz_build(to_dev(p), jz.default_opts(**opts) if opts else None) as t:
+        lab = t.fof(b)
+        torch.cuda.synchronize()
+        return lab.cpu().numpy(), t.stats()
+
+
+def assert_knn_equal(got_i, got_d, want_i, want_d, what=""):
+    bad = np.nonzero(np.any(got_i != want_i, axis=1) | np.any(
+        got_d.view(np.uint32) != want_d.view(np.uint32), axis=1))[0]
+    assert bad.size == 0, "%s: %d rows differ, first %s: got %s %s want %s %s" % (
+        what, bad.size, bad[:1], got_i[bad[:1]], got_d[bad[:1]], want_i[bad[:1]], want_d[bad[:1]])
+
+
+def small_sets():
+    rng = np.random.default_rng(7)
+    yield "uniform-16384", inputs.uniform(16384, 1)
+    yield "uniform-1000", inputs.uniform(1000, 11)
+    yield "clustered-20000", inputs.clustered(20000, 16, 12)
+    yield "grid-dups-3000", (rng.integers(0, 6, size=(3000, 3)) * 0.125).astype(np.float32)
+    yield "lattice-8", inputs.lattice(8)
+    yield "tiny-1", inputs.uniform(1, 2)
+    yield "tiny-47", inputs.uniform(47, 3)
+    yield "tiny-49", inputs.uniform(49, 4)
+    yield "line", np.stack([np.arange(5000) * np.float32(1e-3), np.zeros(5000), np.zeros(5000)],
+                           axis=1).astype(np.float32)
+    yield "all-identical-300", np.full((300, 3), 0.25, dtype=np.float32)
+    yield "negative-wide", (inputs.uniform(4000, 5) * 2e3 - 1e3).astype(np.float32)
+
+
+@pytest.mark.parametrize("k", [1, 8, 16, 32])
+def test_knn_small_sets(jz, k):
+    for name, p in small_sets():
+        gi, gd, _ = gpu_knn(jz, p, k)
+        wi, wd = oracle.knn_bf(p, k)
+        assert_knn_equal(gi, gd, wi, wd, "%s k=%d" % (name, k))
+
+
+def test_knn_config_small_uniform_k8(jz):
+    """N = 16384 uniform, k = 8: the whole result against brute force."""
+    p = inputs.uniform(16384, 1)
+    gi, gd, st = gpu_knn(jz, p, 8)
+    wi, wd = oracle.knn_bf(p, 8)
+    assert_knn_equal(gi, gd, wi, wd)
+    assert st["reruns"] == 0 or st["reruns"] >= 0
+
+
+@pytest.mark.parametrize("leaf_max,k", [(1, 4), (7, 5), (64, 32), (32, 12)])
+def test_knn_tree_shapes(jz, leaf_max, k):
+    p = inputs.clustered(6000, 8, 21)
+    gi, gd, _ = gpu_knn(jz, p, k, leaf_max=leaf_max, ngr=3, n_target=10)
+    wi, wd = oracle.knn_bf(p, k)
+    assert_knn_equal(gi, gd, wi, wd, "leaf_max=%d" % leaf_max)
+
+
+def test_knn_capacity_regrow_same_result(jz):
+    p = inputs.clustered(8000, 8, 22)
+    gi, gd, st = gpu_knn(jz, p, 16, list_per_node=1.0)
+    wi, wd = oracle.knn_bf(p, 16)
+    assert_knn_equal(gi, gd, wi, wd)
+    assert st["reruns"] >= 1
+
+
+def test_knn_capacity_error_without_regrow(jz):
+    p = inputs.uniform(8000, 23)
+    with pytest.raises(jz.JzError) as e:
+        gpu_knn(jz, p, 16, list_per_node=1.0, auto_regrow=0)
+    assert e.value.status == jz.JZ_E_CAPACITY
+
+
+@pytest.mark.parametrize("alpha", [0.0, 0.1, 0.2, 0.5, 1.5])
+def test_fof_small_sets(jz, alpha):
+    for name, p in small_sets():
+        b = inputs.linking_length(p.shape[0], alpha) if alpha > 0 else 0.0
+        got, _ = gpu_fof(jz, p, b)
+        want = oracle.fof_bf(p, b)
+        assert np.array_equal(got, want), (name, alpha, np.nonzero(got != want)[0][:5])
+
+
+def test_fof_lattice_inclusive(jz):
+    p = inputs.lattice(10)
+    a = 2.0 ** -4
+    got, _ = gpu_fof(jz, p, a)
+    assert np.all(got == 0)
+    got, _ = gpu_fof(jz, p, np.nextafter(np.float32(a), np.float32(0)))
+    assert np.array_equal(got, np.arange(p.shape[0]))
+
+
+def test_fof_dense_clumps(jz):
+    p = inputs.clustered(200000, 6, 31, sigma_range=(0.001, 0.003))
+    b = inputs.linking_length(200000, 0.2)
+    got, st = gpu_fof(jz, p, b)
+    want = oracle.fof_kd(p, b)
+    assert np.array_equal(got, want)
+
+
+def test_empty_input(jz):
+    p = np.zeros((0, 3), dtype=np.float32)
+    with jz.jz_build(torch.zeros((0, 3), dtype=torch.float32, device="cuda")) as t:
+        idx, d2 = t.knn(4)
+        lab = t.fof(0.1)
+        assert idx.shape == (0, 4) and lab.shape == (0,)
+    del p
+
+
+def test_errors(jz):
+    p = inputs.uniform(100, 1)
+    p[17, 1] = np.nan
+    with pytest.raises(jz.JzError) as e:
+        jz.jz_build(to_dev(p))
+    assert e.value.status == jz.JZ_E_NONFINITE
+    q = inputs.uniform(100, 1)
+    q[3, 0] = np.inf
+    with pytest.raises(jz.JzError) as e:
+        jz.jz_build(to_dev(q))
+    assert e.value.status == jz.JZ_E_NONFINITE
+    with jz.jz_build(to_dev(inputs.uniform(100, 1))) as t:
+        with pytest.raises(jz.JzError) as e:
+            t.knn(33)
+        assert e.value.status == jz.JZ_E_UNSUPPORTED
+        with pytest.raises(jz.JzError) as e:
+            t.fof(-1.0)
+        assert e.value.status == jz.JZ_E_INVALID
+
+
+def test_tree_against_plane_reference(jz):
+    """Sorted order, Morton keys and every plane's splits against the
+    oracle's plane construction (oracle.planes) on the same keys."""
+    p = inputs.clustered(30000, 12, 41)
+    opts = jz.default_opts(keep_keys=1, n_target=10)
+    with jz.jz_build(to_dev(p), opts) as t:
+        st = t.stats()
+        ex = t.export(order=True, keys=True)
+        want_keys = planes.interleave(planes.quantize(p))
+        order = np.argsort(want_keys, kind="stable")
+        assert np.array_equal(ex["order"], order)
+        assert np.array_equal(ex["keys"], want_keys[order])
+        lv = planes.key_gap_levels(want_keys[order])
+        nmax = [48 * 8 ** q for q in range(st["planes"])]
+        ref = planes.planes(list(lv), nmax)
+        for q in range(st["planes"]):
+            got = t.export(plane=q)["spl"]
+            assert np.array_equal(got, np.array(ref[q])), q
+
+
+def test_forest_equals_standalone(jz):
+    rng = np.random.default_rng(5)
+    sizes = [0, 1, 5, 48, 49, 300, 1000, 4000, 0, 17, 2500]
+    sets = [inputs.clustered(s, max(1, s // 500), seed=100 + i) if s else
+            np.zeros((0, 3), np.float32) for i, s in enumerate(sizes)]
+    off = np.zeros(len(sizes) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(sizes)
+    allp = np.concatenate(sets)
+    b = np.array([inputs.linking_length(max(s, 1), a) for s, a in
+                  zip(sizes, rng.uniform(0.1, 0.8, len(sizes)))], dtype=np.float32)
+    with jz.jz_forest_build(to_dev(allp), off) as f:
+        idx, d2 = f.knn(9)
+        lab = f.fof(b)
+        torch.cuda.synchronize()
+        idx, d2, lab = idx.cpu().numpy(), d2.cpu().numpy(), lab.cpu().numpy()
+    for s, p in enumerate(sets):
+        a, e = off[s], off[s + 1]
+        if e == a:
+            continue
+        wi, wd = oracle.knn_bf(p, 9)
+        assert_knn_equal(idx[a:e], d2[a:e], wi, wd, "set %d" % s)
+        assert np.array_equal(lab[a:e], oracle.fof_bf(p, b[s])), s
+        gi, gd, _ = gpu_knn(jz, p, 9)
+        assert np.array_equal(gi, idx[a:e]) and np.array_equal(gd, d2[a:e])
+
+
+def test_full_size_clustered(jz):
+    """N = 2^24 clustered (the benchmark workload): kNN k=16 on sampled rows
+    against brute force and in full against the exact kd-tree oracle; FoF in
+    full against the kd-tree oracle."""
+    n = 2 ** 24
+    p = inputs.clustered(n, 4096, 2)
+    b = inputs.linking_length(n, 0.2)
+    with jz.jz_build(to_dev(p)) as t:
+        idx, d2 = t.knn(16)
+        lab = t.fof(b)
+        torch.cuda.synchronize()
+        gi, gd, gl = idx.cpu().numpy(), d2.cpu().numpy(), lab.cpu().numpy()
+        del idx, d2, lab
+    rows = np.random.default_rng(9).choice(n, 512, replace=False)
+    wi, wd = oracle.knn_bf(p, 16, rows=rows)
+    assert_knn_equal(gi[rows], gd[rows], wi, wd, "sampled rows")
+    ki, kd = oracle.knn_kd(p, 16)
+    assert_knn_equal(gi, gd, ki, kd, "full kd")
+    assert np.array_equal(gl, oracle.fof_kd(p, b))
