@@ -73,8 +73,11 @@ typedef struct jz_build_opts {
     int n_target;          /* stop adding planes when N / (N_max^(p)/2) < n_target. Default 1000. */
     int ngr;               /* top nodes per super node (NGR of Alg. 1). Default 32, range [1, 64]. */
     int key_bits;          /* Morton bits per dimension. Default 21, range [1, 21]. */
-    float list_per_node;   /* initial interaction-list capacity in entries per node. Default 96. */
-    int auto_regrow;       /* 1 (default): on list overflow grow and rerun; 0: return JZ_E_CAPACITY. */
+    float list_per_node;   /* initial interaction-list capacity in entries per node. Default 96.
+                              With auto_regrow = 1 the library may start larger, from the list
+                              sizes it has seen in this process. */
+    int auto_regrow;       /* 1 (default): on list overflow grow and rerun; 0: use exactly
+                              list_per_node and return JZ_E_CAPACITY on overflow. */
     int keep_keys;         /* 1: keep the sorted Morton keys for jz_tree_export. Default 0. */
 } jz_build_opts;
 

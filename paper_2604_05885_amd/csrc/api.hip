@@ -10,6 +10,8 @@
 #include <map>
 #include <mutex>
 #include <new>
+#include <tuple>
+#include <algorithm>
 #include <unordered_map>
 #include <vector>
 
@@ -39,6 +41,34 @@ jz_status jz_hip_fail(hipError_t e, const char *what, const char *file, int line
 }
 
 bool jz_profiling() { return g_prof; }
+
+// ---------------------------------------------------------------------------
+// learned list capacities
+
+namespace {
+std::mutex g_cap_m;
+std::map<std::tuple<int, int, int>, double> g_cap;
+}  // namespace
+
+double cap_hint(int op, int k, int level) {
+    std::lock_guard<std::mutex> lk(g_cap_m);
+    auto it = g_cap.find(std::make_tuple(op, k, level));
+    return it == g_cap.end() ? 0.0 : it->second;
+}
+
+void cap_learn(int op, int k, int level, double ratio) {
+    std::lock_guard<std::mutex> lk(g_cap_m);
+    double &r = g_cap[std::make_tuple(op, k, level)];
+    if (ratio > r) r = ratio;
+}
+
+int64_t initial_cap(const jz_tree *t, int op, int k, int level) {
+    // with auto_regrow off the capacity is exactly what the options ask for
+    const double hint = t->opts.auto_regrow ? 1.15 * cap_hint(op, k, level) : 0.0;
+    const double ratio = std::max<double>(t->opts.list_per_node, hint);
+    const double c = ratio * (double)t->L[level] + 1024.0;
+    return c > (double)INT32_MAX ? (int64_t)INT32_MAX : (int64_t)c;
+}
 
 // ---------------------------------------------------------------------------
 // Caching device pool. Freed blocks keep an event recorded on the stream that

@@ -230,19 +230,39 @@ __global__ __launch_bounds__(256) void k_leaf_fof(
     if (lane == 0) atomicAdd(stats, (unsigned long long)ev);
 }
 
-// root of every point (read-only find: no other thread writes uf[i] now)
-__global__ void k_flatten_min(int *__restrict__ uf, const float4 *__restrict__ pts, int64_t n,
-                              int *__restrict__ minidx) {
+// Root of every point (a read-only find: no other thread writes uf[i] now)
+// and the smallest input index per root. Points of one group are mostly
+// contiguous in z-order, so the lanes of a wave first combine their values per
+// root and one lane per distinct root issues the atomic.
+__global__ __launch_bounds__(256) void k_flatten_min(int *__restrict__ uf,
+                                                     const float4 *__restrict__ pts, int64_t n,
+                                                     int *__restrict__ minidx) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int x = (int)i;
-    int p = ld_acq(uf + x);
-    while (p != x) {
-        x = p;
-        p = ld_acq(uf + x);
+    const bool valid = i < n;
+    int root = 0, v = INT_MAX;
+    if (valid) {
+        int x = (int)i;
+        int p = ld_acq(uf + x);
+        while (p != x) {
+            x = p;
+            p = ld_acq(uf + x);
+        }
+        root = x;
+        uf[i] = x;
+        v = __float_as_int(pts[i].w);
     }
-    uf[i] = x;
-    atomicMin(minidx + x, __float_as_int(pts[i].w));
+    uint64_t pending = __ballot(valid);
+    while (pending) {
+        const int leader = __ffsll((unsigned long long)pending) - 1;
+        const int r0 = __shfl(root, leader, 64);
+        const bool mine = valid && root == r0;
+        const uint64_t m = __ballot(mine);
+        int vm = mine ? v : INT_MAX;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) vm = min(vm, __shfl_xor(vm, o, 64));
+        if (lane_id() == leader) atomicMin(minidx + r0, vm);
+        pending &= ~m;
+    }
 }
 
 __global__ void k_labels(const int *__restrict__ uf, const float4 *__restrict__ pts, int64_t n,
@@ -283,13 +303,12 @@ jz_status run_fof(jz_tree *t, const float *b2_set_host, int32_t *label, hipStrea
     JZ_TRY(d_uf.get(ac, n * sizeof(int), s));
     JZ_TRY(d_min.get(ac, n * sizeof(int), s));
     unsigned long long *ctr = d_ctr.as<unsigned long long>();
-    DBuf whole[JZ_MAX_PLANES], b2n[JZ_MAX_PLANES];
-    int64_t maxL = 0;
+    DBuf whole[JZ_MAX_PLANES], b2n[JZ_MAX_PLANES], segs[JZ_MAX_PLANES], lists[JZ_MAX_PLANES];
+    int64_t cap[JZ_MAX_PLANES];
     for (int p = 0; p < P; ++p) {
         JZ_TRY(whole[p].get(ac, t->L[p] * sizeof(int), s));
-        if (t->cap[p] == 0) t->cap[p] = (int64_t)(t->opts.list_per_node * (double)t->L[p]) + 1024;
-        if (t->cap[p] > INT_MAX) t->cap[p] = INT_MAX;
-        maxL = std::max<int64_t>(maxL, t->L[p]);
+        JZ_TRY(segs[p].get(ac, t->L[p] * sizeof(int2), s));
+        cap[p] = initial_cap(t, CAP_FOF, 0, p);
     }
     if (sets) {
         JZ_TRY(d_b2set.get(ac, t->nsets * sizeof(float), s));
@@ -302,54 +321,41 @@ jz_status run_fof(jz_tree *t, const float *b2_set_host, int32_t *label, hipStrea
                                                                b2n[p].as<float>());
         }
     }
-    DBuf segA, segB, listA, listB;
-    JZ_TRY(segA.get(ac, maxL * sizeof(int2), s));
-    JZ_TRY(segB.get(ac, maxL * sizeof(int2), s));
     EventSet ev(jz_profiling());
 
+    // Groups only ever merge, so an overflowing run is simply rerun from the
+    // start with larger lists.
     for (;;) {
-        int64_t capmax = 0;
-        for (int p = 0; p < P; ++p) capmax = std::max(capmax, t->cap[p]);
-        JZ_TRY(listA.ensure(ac, capmax * sizeof(int2), s));
-        JZ_TRY(listB.ensure(ac, capmax * sizeof(int2), s));
+        for (int p = 0; p < P; ++p) JZ_TRY(lists[p].ensure(ac, cap[p] * sizeof(int2), s));
         JZ_HIP(hipMemsetAsync(ctr, 0, d_ctr.bytes, s));
         if (ev.on) JZ_HIP(hipEventRecord(ev[0], s));
         k_iota_n<<<blocks_for(n, 256), 256, 0, s>>>(d_uf.as<int>(), n);
         k_fill<<<blocks_for(n, 256), 256, 0, s>>>(d_min.as<int>(), n, INT_MAX);
-        const int2 *seg_in = t->fof_top_seg.as<int2>();
-        const int2 *list_in = t->fof_top_list.as<int2>();
-        const int *par_spl = t->super_spl.as<int>();
-        const int *whole_par = nullptr;
-        int64_t n_par = t->S;
-        DBuf *segs[2] = {&segA, &segB};
-        DBuf *lists[2] = {&listA, &listB};
-        int which = 0;
         for (int p = P - 1; p >= 0; --p) {
+            const bool top = p == P - 1;
+            const int2 *seg_in = top ? t->fof_top_seg.as<int2>() : segs[p + 1].as<int2>();
+            const int2 *list_in = top ? t->fof_top_list.as<int2>() : lists[p + 1].as<int2>();
+            const int *par_spl = top ? t->super_spl.as<int>() : t->spl[p + 1].as<int>();
+            const int *whole_par = top ? nullptr : whole[p + 1].as<int>();
+            const int64_t n_par = top ? t->S : t->L[p + 1];
             const float *bn = sets ? b2n[p].as<float>() : nullptr;
             k_fof_p2n<<<blocks_for(n_par, 4), 256, 0, s>>>(par_spl, t->nodes[p].as<Node>(),
                                                            (int)n_par, whole_par,
                                                            whole[p].as<int>(), d_uf.as<int>(), b2,
                                                            bn);
-            int2 *seg_out = segs[which]->as<int2>();
-            int2 *list_out = lists[which]->as<int2>();
             k_fof_step<<<blocks_for(n_par, 4), 256, 0, s>>>(
                 seg_in, list_in, par_spl, t->nodes[p].as<Node>(), (int)n_par, b2, bn,
-                whole[p].as<int>(), d_uf.as<int>(), seg_out, list_out, ctr + p, t->cap[p]);
-            seg_in = seg_out;
-            list_in = list_out;
-            par_spl = t->spl[p].as<int>();
-            whole_par = whole[p].as<int>();
-            n_par = t->L[p];
-            which ^= 1;
+                whole[p].as<int>(), d_uf.as<int>(), segs[p].as<int2>(), lists[p].as<int2>(),
+                ctr + p, cap[p]);
         }
         k_fof_l2p<<<blocks_for(t->L[0], 4), 256, 0, s>>>(t->nodes[0].as<Node>(), (int)t->L[0],
                                                          whole[0].as<int>(), d_uf.as<int>());
         JZ_HIP(hipGetLastError());
         if (ev.on) JZ_HIP(hipEventRecord(ev[1], s));
         k_leaf_fof<<<blocks_for(t->L[0], 4), 256, 0, s>>>(
-            seg_in, list_in, t->nodes[0].as<Node>(), t->pts4.as<float4>(), (int)t->L[0], b2,
-            sets ? b2n[0].as<float>() : nullptr, whole[0].as<int>(), d_uf.as<int>(),
-            ctr + JZ_MAX_PLANES);
+            segs[0].as<int2>(), lists[0].as<int2>(), t->nodes[0].as<Node>(), t->pts4.as<float4>(),
+            (int)t->L[0], b2, sets ? b2n[0].as<float>() : nullptr, whole[0].as<int>(),
+            d_uf.as<int>(), ctr + JZ_MAX_PLANES);
         if (ev.on) JZ_HIP(hipEventRecord(ev[2], s));
         k_flatten_min<<<blocks_for(n, 256), 256, 0, s>>>(d_uf.as<int>(), t->pts4.as<float4>(), n,
                                                           d_min.as<int>());
@@ -363,21 +369,23 @@ jz_status run_fof(jz_tree *t, const float *b2_set_host, int32_t *label, hipStrea
         JZ_HIP(hipStreamSynchronize(s));
         bool overflow = false;
         for (int p = 0; p < P; ++p) {
-            t->st.list_entries[p] = (int64_t)hc[p];
-            if ((int64_t)hc[p] > t->cap[p]) {
-                overflow = true;
-                if ((int64_t)hc[p] > INT_MAX)
-                    return jz_fail(JZ_E_CAPACITY, "FoF list at plane %d needs %llu entries "
-                                   "(more than 2^31-1)", p, (unsigned long long)hc[p]);
-                const int64_t want = (int64_t)((double)hc[p] * 1.25) + 1024;
-                t->cap[p] = want > INT_MAX ? INT_MAX : want;
-            }
+            if ((int64_t)hc[p] <= cap[p]) continue;
+            overflow = true;
+            if ((int64_t)hc[p] > INT32_MAX)
+                return jz_fail(JZ_E_CAPACITY, "FoF list at plane %d needs %llu entries "
+                               "(more than 2^31-1)", p, (unsigned long long)hc[p]);
+            const double want = (double)hc[p] * 1.15 + 1024.0;
+            cap[p] = want > (double)INT32_MAX ? (int64_t)INT32_MAX : (int64_t)want;
         }
         if (overflow) {
             if (!t->opts.auto_regrow)
                 return jz_fail(JZ_E_CAPACITY, "FoF interaction list overflow; raise list_per_node");
             t->st.reruns++;
             continue;
+        }
+        for (int p = 0; p < P; ++p) {
+            t->st.list_entries[p] = (int64_t)hc[p];
+            cap_learn(CAP_FOF, 0, p, (double)hc[p] / (double)std::max<int64_t>(1, t->L[p]));
         }
         t->st.leaf_pairs = t->st.list_entries[0];
         t->st.evaluations = (double)hc[JZ_MAX_PLANES];

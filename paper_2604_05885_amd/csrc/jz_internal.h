@@ -118,9 +118,6 @@ struct jz_tree {
     DBuf knn_top_seg, knn_top_list;  // dense super-node list (all pairs within a set)
     DBuf fof_top_seg, fof_top_list;  // dense super-node list (pairs s <= t within a set)
 
-    // interaction-list capacity per level (entries), grown on overflow
-    int64_t cap[JZ_MAX_PLANES] = {};
-
     jz_stats st{};
 };
 
@@ -130,6 +127,14 @@ jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s);
 jz_status run_fof(jz_tree *t, const float *b2_set_host, int32_t *label, hipStream_t s);
 
 bool jz_profiling();
+
+// Process-wide memory of interaction-list sizes: the largest entries-per-node
+// ratio seen for (operation, k, level), so that later calls on similar data
+// start with lists that are large enough.
+enum { CAP_KNN = 0, CAP_FOF = 1 };
+double cap_hint(int op, int k, int level);
+void cap_learn(int op, int k, int level, double ratio);
+int64_t initial_cap(const jz_tree *t, int op, int k, int level);
 
 // hipEvents for optional device timing; created only when profiling is on
 struct EventSet {

@@ -225,6 +225,27 @@ __device__ __forceinline__ void topk_insert(uint64_t (&b)[K], uint64_t key) {
     }
 }
 
+// lower bound of dist2 from a point to any point of a box (monotone, exact)
+__device__ __forceinline__ float point_box_low2(const float4 &q, const Node &b) {
+    const float gx = fmaxf(fmaxf(b.lo[0] - q.x, q.x - b.hi[0]), 0.0f);
+    const float gy = fmaxf(fmaxf(b.lo[1] - q.y, q.y - b.hi[1]), 0.0f);
+    const float gz = fmaxf(fmaxf(b.lo[2] - q.z, q.z - b.hi[2]), 0.0f);
+    const float xx = gx * gx;
+    const float yy = gy * gy;
+    const float zz = gz * gz;
+    const float s = xx + yy;
+    return s + zz;
+}
+
+constexpr int CQ = 8;  // queued candidates per lane between insert rounds
+
+// Leaf stage. Per source leaf (in r_low order): stop when r_low exceeds every
+// lane's current k-th distance; skip the leaf when no lane's point-to-box
+// bound reaches its k-th distance; otherwise stage the leaf's points in LDS
+// and test them against the lane's k-th key. Passing candidates are queued in
+// LDS (CQ per lane) and inserted into the register top-k in rounds, so a wave
+// spends insert time in proportion to its busiest lane rather than to every
+// candidate that any lane accepts.
 template <int K>
 __global__ __launch_bounds__(256) void k_leaf_knn(
     const int2 *__restrict__ seg, const int2 *__restrict__ list, const Node *__restrict__ leaves,
@@ -233,6 +254,7 @@ __global__ __launch_bounds__(256) void k_leaf_knn(
     unsigned long long *__restrict__ stats) {
     __shared__ uint64_t s_list[4][LCAP];
     __shared__ float4 s_tile[4][64];
+    __shared__ uint64_t s_q[4][CQ][64];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int A = xcd_block(blockIdx.x, gridDim.x) * 4 + w;
     if (A >= n_leaves) return;
@@ -250,6 +272,7 @@ __global__ __launch_bounds__(256) void k_leaf_knn(
     uint64_t best[K];
 #pragma unroll
     for (int i = 0; i < K; ++i) best[i] = PAD_KEY;
+    int qn = 0;  // queued candidates of this lane
     unsigned evals = 0, visited = 0;
     for (int t = 0; t < len; ++t) {
         int src;
@@ -257,20 +280,37 @@ __global__ __launch_bounds__(256) void k_leaf_knn(
         list_entry(staged, L, gl, t, src, rl);
         const float kth = __uint_as_float((uint32_t)(best[K - 1] >> 32));
         if (staged && rl > wave_max(act ? kth : -INFINITY)) break;
-        ++visited;
         const Node b = leaves[src];
+        const bool need = act && point_box_low2(me, b) <= kth;
+        if (!__ballot(need)) continue;
+        ++visited;
         const int e1 = b.start + b.count;
         for (int sb = b.start; sb < e1; sb += 64) {
             const int ns = min(64, e1 - sb);
             if (lane < ns) tile[lane] = pts[sb + lane];
             wave_lds_sync();
-            for (int j = 0; j < ns; ++j) {
-                const float4 s = tile[j];
-                const float dd = dist2_pts(me.x, me.y, me.z, s.x, s.y, s.z);
-                const uint64_t key = ((uint64_t)__float_as_uint(dd) << 32) | (uint32_t)__float_as_int(s.w);
-                if (act && key < best[K - 1]) topk_insert<K>(best, key);
+            const uint64_t thr = best[K - 1];
+            for (int j0 = 0; j0 < ns; j0 += CQ) {
+                const int j1 = min(ns, j0 + CQ);
+                for (int j = j0; j < j1; ++j) {
+                    const float4 s = tile[j];
+                    const float dd = dist2_pts(me.x, me.y, me.z, s.x, s.y, s.z);
+                    const uint64_t key =
+                        ((uint64_t)__float_as_uint(dd) << 32) | (uint32_t)__float_as_int(s.w);
+                    if (need && key < thr) s_q[w][qn++][lane] = key;
+                }
+                // insert round: every lane drains its queue
+                if (__ballot(qn > 0)) {
+                    for (int c = 0; __ballot(c < qn); ++c) {
+                        if (c < qn) {
+                            const uint64_t key = s_q[w][c][lane];
+                            if (key < best[K - 1]) topk_insert<K>(best, key);
+                        }
+                    }
+                    qn = 0;
+                }
             }
-            evals += act ? ns : 0;
+            evals += need ? ns : 0;
             wave_lds_sync();
         }
     }
@@ -326,81 +366,79 @@ jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s) 
     t->st.reruns = 0;
     if (t->n == 0) return JZ_OK;
 
+    // counters: [0, P) list entries per level, [JZ_MAX_PLANES, +2) leaf stats
     DBuf d_ctr;
     JZ_TRY(d_ctr.get(ac, (JZ_MAX_PLANES + 4) * sizeof(unsigned long long), s));
     unsigned long long *ctr = d_ctr.as<unsigned long long>();
-    int64_t maxL = 0;
+    JZ_HIP(hipMemsetAsync(ctr, 0, d_ctr.bytes, s));
+    int64_t cap[JZ_MAX_PLANES];
+    DBuf segs[JZ_MAX_PLANES], lists[JZ_MAX_PLANES];
     for (int p = 0; p < P; ++p) {
-        if (t->cap[p] == 0) t->cap[p] = (int64_t)(t->opts.list_per_node * (double)t->L[p]) + 1024;
-        if (t->cap[p] > INT_MAX) t->cap[p] = INT_MAX;
-        maxL = std::max<int64_t>(maxL, t->L[p]);
+        cap[p] = initial_cap(t, CAP_KNN, k, p);
+        JZ_TRY(segs[p].get(ac, t->L[p] * sizeof(int2), s));
     }
-    DBuf segA, segB, listA, listB;
-    JZ_TRY(segA.get(ac, maxL * sizeof(int2), s));
-    JZ_TRY(segB.get(ac, maxL * sizeof(int2), s));
     EventSet ev(jz_profiling());
-    const bool prof = ev.on;
 
-    for (int attempt = 0;; ++attempt) {
-        int64_t capmax = 0;
-        for (int p = 0; p < P; ++p) capmax = std::max(capmax, t->cap[p]);
-        JZ_TRY(listA.ensure(ac, capmax * sizeof(int2), s));
-        JZ_TRY(listB.ensure(ac, capmax * sizeof(int2), s));
-        JZ_HIP(hipMemsetAsync(ctr, 0, d_ctr.bytes, s));
-        if (prof) JZ_HIP(hipEventRecord(ev[0], s));
-        const int2 *seg_in = t->knn_top_seg.as<int2>();
-        const int2 *list_in = t->knn_top_list.as<int2>();
-        const int *par_spl = t->super_spl.as<int>();
-        int64_t n_par = t->S;
-        DBuf *segs[2] = {&segA, &segB};
-        DBuf *lists[2] = {&listA, &listB};
-        int which = 0;
-        for (int p = P - 1; p >= 0; --p) {
-            int2 *seg_out = segs[which]->as<int2>();
-            int2 *list_out = lists[which]->as<int2>();
+    // Level p turns the list of plane p+1 (or of the super nodes) into the
+    // list of plane p. On overflow, levels from the highest overflowing one
+    // down are rerun with larger lists; the levels above are still valid.
+    int start = P - 1;
+    for (;;) {
+        for (int p = start; p >= 0; --p) JZ_TRY(lists[p].ensure(ac, cap[p] * sizeof(int2), s));
+        if (ev.on) JZ_HIP(hipEventRecord(ev[0], s));
+        for (int p = start; p >= 0; --p) {
+            const bool top = p == P - 1;
+            const int2 *seg_in = top ? t->knn_top_seg.as<int2>() : segs[p + 1].as<int2>();
+            const int2 *list_in = top ? t->knn_top_list.as<int2>() : lists[p + 1].as<int2>();
+            const int *par_spl = top ? t->super_spl.as<int>() : t->spl[p + 1].as<int>();
+            const int64_t n_par = top ? t->S : t->L[p + 1];
             k_knn_step<<<blocks_for(n_par, 4), 256, 0, s>>>(seg_in, list_in, par_spl,
                                                             t->nodes[p].as<Node>(), (int)n_par, k,
-                                                            seg_out, list_out, ctr + p, t->cap[p]);
-            seg_in = seg_out;
-            list_in = list_out;
-            par_spl = t->spl[p].as<int>();
-            n_par = t->L[p];
-            which ^= 1;
+                                                            segs[p].as<int2>(), lists[p].as<int2>(),
+                                                            ctr + p, cap[p]);
         }
         JZ_HIP(hipGetLastError());
-        if (prof) JZ_HIP(hipEventRecord(ev[1], s));
+        if (ev.on) JZ_HIP(hipEventRecord(ev[1], s));
         leaf_kernel(k)<<<blocks_for(t->L[0], 4), 256, 0, s>>>(
-            seg_in, list_in, t->nodes[0].as<Node>(), t->pts4.as<float4>(), (int)t->L[0],
-            t->nsets > 1 ? t->leaf_base.as<int>() : nullptr, idx, dist2, ctr + JZ_MAX_PLANES);
+            segs[0].as<int2>(), lists[0].as<int2>(), t->nodes[0].as<Node>(), t->pts4.as<float4>(),
+            (int)t->L[0], t->nsets > 1 ? t->leaf_base.as<int>() : nullptr, idx, dist2,
+            ctr + JZ_MAX_PLANES);
         JZ_HIP(hipGetLastError());
-        if (prof) JZ_HIP(hipEventRecord(ev[2], s));
+        if (ev.on) JZ_HIP(hipEventRecord(ev[2], s));
         unsigned long long hc[JZ_MAX_PLANES + 4];
         JZ_HIP(hipMemcpyAsync(hc, ctr, sizeof(hc), hipMemcpyDeviceToHost, s));
         JZ_HIP(hipStreamSynchronize(s));
-        bool overflow = false;
-        for (int p = 0; p < P; ++p) {
-            t->st.list_entries[p] = (int64_t)hc[p];
-            if ((int64_t)hc[p] > t->cap[p]) {
-                overflow = true;
-                int64_t want = (int64_t)((double)hc[p] * 1.25) + 1024;
-                t->cap[p] = want > INT_MAX ? INT_MAX : want;
-                if ((int64_t)hc[p] > INT_MAX)
-                    return jz_fail(JZ_E_CAPACITY, "interaction list at plane %d needs %llu entries "
-                                   "(more than 2^31-1)", p, (unsigned long long)hc[p]);
-            }
+        int redo = -1;
+        for (int p = start; p >= 0; --p) {
+            if ((int64_t)hc[p] <= cap[p]) continue;
+            if ((int64_t)hc[p] > INT32_MAX)
+                return jz_fail(JZ_E_CAPACITY, "interaction list at plane %d needs %llu entries "
+                               "(more than 2^31-1)", p, (unsigned long long)hc[p]);
+            if (redo < 0) redo = p;
+            const double want = (double)hc[p] * 1.15 + 1024.0;
+            cap[p] = want > (double)INT32_MAX ? (int64_t)INT32_MAX : (int64_t)want;
         }
-        if (overflow) {
+        if (redo >= 0) {
             if (!t->opts.auto_regrow)
                 return jz_fail(JZ_E_CAPACITY,
-                               "interaction list overflow; set list_per_node to at least %.1f",
-                               (double)t->cap[0] / (double)std::max<int64_t>(1, t->L[0]));
+                               "interaction list overflow at plane %d; list_per_node must be at "
+                               "least %.1f", redo, (double)hc[redo] / (double)t->L[redo]);
             t->st.reruns++;
+            start = redo;
+            // clear the counters of the levels to redo and the leaf statistics
+            for (int p = 0; p <= start; ++p) hc[p] = 0;
+            JZ_HIP(hipMemcpyAsync(ctr, hc, sizeof(hc), hipMemcpyHostToDevice, s));
+            JZ_HIP(hipMemsetAsync(ctr + JZ_MAX_PLANES, 0, 4 * sizeof(unsigned long long), s));
             continue;
+        }
+        for (int p = 0; p < P; ++p) {
+            t->st.list_entries[p] = (int64_t)hc[p];
+            cap_learn(CAP_KNN, k, p, (double)hc[p] / (double)std::max<int64_t>(1, t->L[p]));
         }
         t->st.leaf_pairs = t->st.list_entries[0];
         t->st.evaluations = (double)hc[JZ_MAX_PLANES];
         t->st.leaf_pairs_visited = (int64_t)hc[JZ_MAX_PLANES + 1];
-        if (prof) {
+        if (ev.on) {
             float ms = 0;
             JZ_HIP(hipEventElapsedTime(&ms, ev[1], ev[2]));
             t->st.leaf_ms = ms;
