@@ -50,19 +50,28 @@ __global__ __launch_bounds__(256) void k_bbox(const float *__restrict__ pts, int
             hi[a] = fmaxf(hi[a], v);
         }
     }
+    // one atomic per block and value (same-address atomics serialize in L2)
+    __shared__ float s_v[4][7];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         lo[a] = wave_min(lo[a]);
         hi[a] = wave_max(hi[a]);
     }
     bad = wave_sum(bad);
+    const int w = threadIdx.x >> 6;
     if (lane_id() == 0) {
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            atomicMin(bbox + a, f2o(lo[a]));
-            atomicMax(bbox + 3 + a, f2o(hi[a]));
-        }
-        if (bad) atomicOr(bbox + 6, 1);
+        s_v[w][0] = lo[0]; s_v[w][1] = lo[1]; s_v[w][2] = lo[2];
+        s_v[w][3] = hi[0]; s_v[w][4] = hi[1]; s_v[w][5] = hi[2];
+        s_v[w][6] = bad ? 1.0f : 0.0f;
+    }
+    __syncthreads();
+    if (threadIdx.x < 7) {
+        const int a = threadIdx.x;
+        float v = s_v[0][a];
+        for (int ww = 1; ww < 4; ++ww) v = a < 3 ? fminf(v, s_v[ww][a]) : fmaxf(v, s_v[ww][a]);
+        if (a < 3) atomicMin(bbox + a, f2o(v));
+        else if (a < 6) atomicMax(bbox + a, f2o(v));
+        else if (v != 0.0f) atomicOr(bbox + 6, 1);
     }
 }
 
@@ -611,7 +620,7 @@ jz_status build_tree(jz_tree *t, const float *points, hipStream_t s) {
         JZ_HIP(hipMemcpyAsync(d_bbox.p, init, sizeof(init), hipMemcpyHostToDevice, s));
         JZ_HIP(hipMemsetAsync(d_hist.p, 0, d_hist.bytes, s));
     }
-    const unsigned gb = std::min<unsigned>(blocks_for(n, 256), 2048);
+    const unsigned gb = std::min<unsigned>(blocks_for(n, 256), 1024);
     k_bbox<<<gb, 256, 0, s>>>(points, n, d_bbox.as<int>());
     k_morton<<<std::min<unsigned>(blocks_for(n, 256 * 8), 2048), 256, 0, s>>>(
         points, n, d_bbox.as<int>(), bits, t->d_set_off.as<int64_t>(), t->nsets, npass,

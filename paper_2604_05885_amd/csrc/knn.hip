@@ -109,14 +109,89 @@ __device__ __forceinline__ float radius_of_count(const float (&hr)[NR], const in
 }
 
 constexpr int NR_HEAP = 8;
+constexpr int FCAP = 128;  // source children staged per batch
 
+// Walk the (r_low-sorted) source list of one receiving parent in batches: the
+// children of consecutive sources are copied into one LDS buffer (their node
+// records in F, their indices in FI) until FCAP children; a source with more
+// children than FCAP is split over several batches. Sources whose r_low
+// exceeds rw() (re-evaluated per batch) end the walk. fn(nF) then processes
+// the nF staged children.
+template <class RW, class FN>
+__device__ __forceinline__ void for_source_batches(bool staged, const uint64_t *L,
+                                                   const int2 *gl, int len,
+                                                   const int *__restrict__ par_spl,
+                                                   const Node *__restrict__ nodes, Node *F, int *FI,
+                                                   RW &&rw, FN &&fn) {
+    const int lane = lane_id();
+    int t = 0, skip = 0;
+    while (t < len) {
+        const float Rw = rw();
+        int src = 0, s0 = 0, cnt = 0;
+        float rl = 0.0f;
+        const bool valid = t + lane < len;
+        if (valid) {
+            list_entry(staged, L, gl, t + lane, src, rl);
+            s0 = par_spl[src];
+            cnt = par_spl[src + 1] - s0;
+            if (lane == 0) {
+                s0 += skip;
+                cnt -= skip;
+            }
+        }
+        const bool ok = valid && (!staged || rl <= Rw);
+        const uint64_t okm = __ballot(ok);  // sorted by r_low: a prefix of the lanes
+        const int nok = ~okm ? __ffsll((unsigned long long)~okm) - 1 : 64;
+        if (nok == 0) break;
+        const int c = lane < nok ? cnt : 0;
+        const int incl = wave_incl_scan(c);
+        const int ntake = __popcll(__ballot(lane < nok && incl <= FCAP));
+        int nF;
+        if (ntake == 0) {
+            // the first source alone overflows the buffer: take FCAP of its children
+            const int b0 = __shfl(s0, 0, 64);
+            for (int f = lane; f < FCAP; f += 64) {
+                F[f] = nodes[b0 + f];
+                FI[f] = b0 + f;
+            }
+            nF = FCAP;
+            skip += FCAP;
+        } else {
+            if (lane < ntake) {
+                const int off = incl - c;
+                for (int q = 0; q < c; ++q) {
+                    F[off + q] = nodes[s0 + q];
+                    FI[off + q] = s0 + q;
+                }
+            }
+            nF = __shfl(incl, ntake - 1, 64);
+            t += ntake;
+            skip = 0;
+        }
+        wave_lds_sync();
+        fn(nF);
+        wave_lds_sync();
+    }
+}
+
+// Level step of the kNN walk: one wave per receiving parent. Its children are
+// spread over the lanes with G = 64 / (children, rounded up to a power of 2)
+// lanes per child; the G lanes of a child split the staged source children
+// between them (slice sl takes f = sl, sl + G, ...).
+//   pass 1  FindRmax: a register heap of (d_up^2, count) per lane; the G
+//           heaps of a child are then merged exactly in LDS (R = smallest
+//           radius whose cumulative count over all entries reaches k)
+//   pass 2  count pairs with d_low^2 <= R
+//   pass 3  insert them (with r_low = d_low^2) at offsets reserved with one
+//           atomic per wave; a child's entries are contiguous.
 __global__ __launch_bounds__(256) void k_knn_step(
     const int2 *__restrict__ seg_in, const int2 *__restrict__ list_in,
     const int *__restrict__ par_spl, const Node *__restrict__ nodes, int n_par, int k,
     int2 *__restrict__ seg_out, int2 *__restrict__ list_out,
     unsigned long long *__restrict__ ctr, long long cap) {
     __shared__ uint64_t s_list[4][LCAP];
-    __shared__ Node s_tile[4][64];
+    __shared__ Node s_f[4][FCAP];
+    __shared__ int s_fi[4][FCAP];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int P = xcd_block(blockIdx.x, gridDim.x) * 4 + w;
     if (P >= n_par) return;
@@ -125,14 +200,21 @@ __global__ __launch_bounds__(256) void k_knn_step(
     const int len = sg.y;
     const int c0 = par_spl[P], c1 = par_spl[P + 1];
     uint64_t *L = s_list[w];
-    Node *tile = s_tile[w];
+    Node *F = s_f[w];
+    int *FI = s_fi[w];
     const bool staged = len <= LCAP;
     if (staged) stage_sorted(gl, len, L);
 
     for (int cb = c0; cb < c1; cb += 64) {
-        const int c = cb + lane;
-        const bool act = c < c1;
-        const Node me = nodes[act ? c : c0];
+        const int nc = min(64, c1 - cb);
+        // G = largest power of two with nc * G <= 64
+        int lg = 0;
+        while ((nc << (lg + 1)) <= 64) ++lg;
+        const int G = 1 << lg;
+        const int ci = lane >> lg, sl = lane & (G - 1);
+        const bool act = ci < nc;
+        const int c = cb + (act ? ci : 0);
+        const Node me = nodes[c];
         float hr[NR_HEAP];
         int hc[NR_HEAP];
 #pragma unroll
@@ -141,77 +223,82 @@ __global__ __launch_bounds__(256) void k_knn_step(
             hc[i] = 0;
         }
         float R = INFINITY;
-        // pass 1: FindRmax
-        for (int t = 0; t < len; ++t) {
-            int src;
-            float rl;
-            list_entry(staged, L, gl, t, src, rl);
-            if (staged && rl > wave_max(act ? R : -INFINITY)) break;
-            const int s0 = par_spl[src], s1 = par_spl[src + 1];
-            for (int sb = s0; sb < s1; sb += 64) {
-                const int ns = min(64, s1 - sb);
-                if (lane < ns) tile[lane] = nodes[sb + lane];
-                wave_lds_sync();
-                for (int j = 0; j < ns; ++j) {
-                    const Node o = tile[j];
+        // pass 1: FindRmax over this lane's slice
+        for_source_batches(
+            staged, L, gl, len, par_spl, nodes, F, FI,
+            [&]() { return wave_max(act ? R : -INFINITY); },
+            [&](int nF) {
+                for (int f = sl; f < nF; f += G) {
+                    const Node o = F[f];
                     const float r = box_up2(me, o);
                     if (act && r < R) {
                         heap_insert<NR_HEAP>(hr, hc, r, o.count);
                         R = radius_of_count<NR_HEAP>(hr, hc, k);
                     }
                 }
-                wave_lds_sync();
+            });
+        if (G > 1) {
+            // exact merge of the G heaps of each child (LDS scratch: F's buffer)
+            float *mr = reinterpret_cast<float *>(F);
+            int *mc = reinterpret_cast<int *>(F) + NR_HEAP * 64;
+#pragma unroll
+            for (int i = 0; i < NR_HEAP; ++i) {
+                mr[i * 64 + lane] = hr[i];
+                mc[i * 64 + lane] = hc[i];
             }
+            wave_lds_sync();
+            float best = INFINITY;
+            const int g0 = ci << lg;
+            if (act) {
+                for (int e = sl; e < G * NR_HEAP; e += G) {
+                    const float re = mr[(e % NR_HEAP) * 64 + g0 + e / NR_HEAP];
+                    if (!(re < best)) continue;
+                    int acc = 0;
+                    for (int g = 0; g < G; ++g)
+                        for (int i = 0; i < NR_HEAP; ++i)
+                            if (mr[i * 64 + g0 + g] <= re) acc += mc[i * 64 + g0 + g];
+                    if (acc >= k) best = re;
+                }
+            }
+            for (int o = 1; o < G; o <<= 1) best = fminf(best, __shfl_xor(best, o, 64));
+            R = best;
+            wave_lds_sync();
         }
         const float Rw = wave_max(act ? R : -INFINITY);
         // pass 2: count
         int cnt = 0;
-        for (int t = 0; t < len; ++t) {
-            int src;
-            float rl;
-            list_entry(staged, L, gl, t, src, rl);
-            if (staged && rl > Rw) break;
-            const int s0 = par_spl[src], s1 = par_spl[src + 1];
-            for (int sb = s0; sb < s1; sb += 64) {
-                const int ns = min(64, s1 - sb);
-                if (lane < ns) tile[lane] = nodes[sb + lane];
-                wave_lds_sync();
-                for (int j = 0; j < ns; ++j) cnt += (act && box_low2(me, tile[j]) <= R) ? 1 : 0;
-                wave_lds_sync();
-            }
-        }
-        // reserve
+        for_source_batches(
+            staged, L, gl, len, par_spl, nodes, F, FI, [&]() { return Rw; },
+            [&](int nF) {
+                for (int f = sl; f < nF; f += G) cnt += (act && box_low2(me, F[f]) <= R) ? 1 : 0;
+            });
+        // reserve: lanes are child-major, so a wave scan gives contiguous segments
         const int incl = wave_incl_scan(cnt);
         const int total = __shfl(incl, 63, 64);
         unsigned long long base = 0;
         if (lane == 0) base = atomicAdd(ctr, (unsigned long long)total);
         base = __shfl(base, 0, 64);
-        const long long pos = (long long)base + (incl - cnt);
         const bool ok = (long long)base + total <= cap;
-        if (act) seg_out[c] = ok ? make_int2((int)pos, cnt) : make_int2(0, 0);
+        const int gfirst = (ci << lg), glast = gfirst + G - 1;
+        const int gstart = __shfl(incl - cnt, gfirst & 63, 64);
+        const int gend = __shfl(incl, glast & 63, 64);
+        if (act && sl == 0)
+            seg_out[c] = ok ? make_int2((int)((long long)base + gstart), gend - gstart)
+                            : make_int2(0, 0);
         if (!ok) continue;
         // pass 3: insert
-        long long wp = pos;
-        for (int t = 0; t < len; ++t) {
-            int src;
-            float rl;
-            list_entry(staged, L, gl, t, src, rl);
-            if (staged && rl > Rw) break;
-            const int s0 = par_spl[src], s1 = par_spl[src + 1];
-            for (int sb = s0; sb < s1; sb += 64) {
-                const int ns = min(64, s1 - sb);
-                if (lane < ns) tile[lane] = nodes[sb + lane];
-                wave_lds_sync();
-                for (int j = 0; j < ns; ++j) {
-                    const float lo = box_low2(me, tile[j]);
+        long long wp = (long long)base + (incl - cnt);
+        for_source_batches(
+            staged, L, gl, len, par_spl, nodes, F, FI, [&]() { return Rw; },
+            [&](int nF) {
+                for (int f = sl; f < nF; f += G) {
+                    const float lo = box_low2(me, F[f]);
                     if (act && lo <= R) {
-                        list_out[wp] = make_int2(sb + j, __float_as_int(lo));
+                        list_out[wp] = make_int2(FI[f], __float_as_int(lo));
                         ++wp;
                     }
                 }
-                wave_lds_sync();
-            }
-        }
+            });
     }
 }
 
@@ -237,15 +324,20 @@ __device__ __forceinline__ float point_box_low2(const float4 &q, const Node &b) 
     return s + zz;
 }
 
-constexpr int CQ = 8;  // queued candidates per lane between insert rounds
+constexpr int CQ = 8;         // queued candidates per lane between insert rounds
+constexpr int SB = 8;         // source leaves examined per batch
+constexpr int TILE_PTS = 128; // source points staged per batch
 
-// Leaf stage. Per source leaf (in r_low order): stop when r_low exceeds every
-// lane's current k-th distance; skip the leaf when no lane's point-to-box
-// bound reaches its k-th distance; otherwise stage the leaf's points in LDS
-// and test them against the lane's k-th key. Passing candidates are queued in
-// LDS (CQ per lane) and inserted into the register top-k in rounds, so a wave
-// spends insert time in proportion to its busiest lane rather than to every
-// candidate that any lane accepts.
+// Leaf stage, one wave per receiving leaf (lanes = its query points).
+// Source leaves are taken in r_low order, in batches: the Node records of up to
+// SB sources are read together; each lane marks the sources its query can
+// still reach (point-to-box bound <= its current k-th distance); the points of
+// the sources some lane needs are staged together in one LDS tile; then every
+// lane tests them against its k-th key. The walk stops at the first source
+// whose r_low exceeds every lane's k-th distance. Accepted candidates are
+// queued in LDS (CQ per lane) and inserted into the register top-k in rounds,
+// so insert time follows the busiest lane rather than every accepted
+// candidate of any lane.
 template <int K>
 __global__ __launch_bounds__(256) void k_leaf_knn(
     const int2 *__restrict__ seg, const int2 *__restrict__ list, const Node *__restrict__ leaves,
@@ -253,7 +345,9 @@ __global__ __launch_bounds__(256) void k_leaf_knn(
     int32_t *__restrict__ out_idx, float *__restrict__ out_d2,
     unsigned long long *__restrict__ stats) {
     __shared__ uint64_t s_list[4][LCAP];
-    __shared__ float4 s_tile[4][64];
+    __shared__ float4 s_tile[4][TILE_PTS];
+    __shared__ Node s_nodes[4][SB];
+    __shared__ int s_offs[4][SB + 1];
     __shared__ uint64_t s_q[4][CQ][64];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int A = xcd_block(blockIdx.x, gridDim.x) * 4 + w;
@@ -266,32 +360,65 @@ __global__ __launch_bounds__(256) void k_leaf_knn(
     const int len = sg.y;
     uint64_t *L = s_list[w];
     float4 *tile = s_tile[w];
+    Node *nb = s_nodes[w];
+    int *offs = s_offs[w];
     const bool staged = len <= LCAP;
     if (staged) stage_sorted(gl, len, L);
 
     uint64_t best[K];
 #pragma unroll
     for (int i = 0; i < K; ++i) best[i] = PAD_KEY;
-    int qn = 0;  // queued candidates of this lane
     unsigned evals = 0, visited = 0;
-    for (int t = 0; t < len; ++t) {
-        int src;
-        float rl;
-        list_entry(staged, L, gl, t, src, rl);
+    int t = 0;
+    while (t < len) {
         const float kth = __uint_as_float((uint32_t)(best[K - 1] >> 32));
-        if (staged && rl > wave_max(act ? kth : -INFINITY)) break;
-        const Node b = leaves[src];
-        const bool need = act && point_box_low2(me, b) <= kth;
-        if (!__ballot(need)) continue;
-        ++visited;
-        const int e1 = b.start + b.count;
-        for (int sb = b.start; sb < e1; sb += 64) {
-            const int ns = min(64, e1 - sb);
-            if (lane < ns) tile[lane] = pts[sb + lane];
-            wave_lds_sync();
-            const uint64_t thr = best[K - 1];
-            for (int j0 = 0; j0 < ns; j0 += CQ) {
-                const int j1 = min(ns, j0 + CQ);
+        const float Rw = wave_max(act ? kth : -INFINITY);
+        // sources t .. t + nb_n - 1 of this batch (all with r_low <= Rw)
+        int src = 0;
+        float rl = INFINITY;
+        if (lane < SB && t + lane < len) list_entry(staged, L, gl, t + lane, src, rl);
+        const bool inb = lane < SB && t + lane < len && (!staged || rl <= Rw);
+        const uint64_t inmask = __ballot(inb);
+        // sources are sorted by r_low: the batch is a prefix; an empty one ends the walk
+        const int nb_n = __ffsll((unsigned long long)(~inmask)) - 1;
+        if (nb_n == 0) break;
+        if (lane < nb_n) nb[lane] = leaves[src];
+        wave_lds_sync();
+        // per-lane need bits; which sources any lane needs
+        unsigned needbits = 0;
+        for (int q = 0; q < nb_n; ++q)
+            if (act && point_box_low2(me, nb[q]) <= kth) needbits |= 1u << q;
+        unsigned any = needbits;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) any |= __shfl_xor(any, o, 64);
+        // take needed sources in order while their points fit the tile
+        // (every lane computes the same offsets; lane 0 keeps them in LDS)
+        int take = 0, npts = 0;
+        if (lane == 0) offs[0] = 0;
+        for (int q = 0; q < nb_n; ++q) {
+            const int c = (any >> q) & 1u ? nb[q].count : 0;
+            if (npts + c > TILE_PTS) break;
+            npts += c;
+            if (lane == 0) offs[q + 1] = npts;
+            take = q + 1;
+        }
+        wave_lds_sync();
+        // stage the points of the taken sources
+        for (int f = lane; f < npts; f += 64) {
+            int q = 0;
+            while (offs[q + 1] <= f) ++q;
+            tile[f] = pts[nb[q].start + (f - offs[q])];
+        }
+        wave_lds_sync();
+        const uint64_t thr = best[K - 1];
+        int qn = 0;
+        for (int q = 0; q < take; ++q) {
+            if (!((any >> q) & 1u)) continue;
+            ++visited;
+            const bool need = (needbits >> q) & 1u;
+            const int f0 = offs[q], f1 = offs[q + 1];
+            for (int j0 = f0; j0 < f1; j0 += CQ) {
+                const int j1 = min(f1, j0 + CQ);
                 for (int j = j0; j < j1; ++j) {
                     const float4 s = tile[j];
                     const float dd = dist2_pts(me.x, me.y, me.z, s.x, s.y, s.z);
@@ -299,7 +426,6 @@ __global__ __launch_bounds__(256) void k_leaf_knn(
                         ((uint64_t)__float_as_uint(dd) << 32) | (uint32_t)__float_as_int(s.w);
                     if (need && key < thr) s_q[w][qn++][lane] = key;
                 }
-                // insert round: every lane drains its queue
                 if (__ballot(qn > 0)) {
                     for (int c = 0; __ballot(c < qn); ++c) {
                         if (c < qn) {
@@ -310,9 +436,10 @@ __global__ __launch_bounds__(256) void k_leaf_knn(
                     qn = 0;
                 }
             }
-            evals += need ? ns : 0;
-            wave_lds_sync();
+            evals += need ? (unsigned)(f1 - f0) : 0u;
         }
+        wave_lds_sync();
+        t += take;
     }
     if (act) {
         const int64_t row = (int64_t)__float_as_int(me.w);
