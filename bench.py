@@ -45,6 +45,16 @@ def parse():
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "leaf_knn_traffic.json"),
                     help="HBM bytes per launch of the dominant kernel from rocprofv3 counters")
+    ap.add_argument("--mode", choices=["step", "batched", "served"], default="step",
+                    help="step: N=2^24 kNN+FoF (default); batched: many sets in one forest vs "
+                         "per-set launches; served: Poisson request stream")
+    ap.add_argument("--sets", type=int, default=4096, help="batched: number of sets")
+    ap.add_argument("--rate", type=float, default=2000.0, help="served: requests per second")
+    ap.add_argument("--duration", type=float, default=10.0, help="served: seconds of arrivals")
+    ap.add_argument("--measure-after", type=float, default=2.0,
+                    help="served: arrivals before this time (s) are warm-up")
+    ap.add_argument("--pool", type=int, default=64, help="served: distinct point sets")
+    ap.add_argument("--streams", type=int, default=4, help="served: server worker streams")
     return ap.parse_args()
 
 
@@ -54,6 +64,10 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.mode == "batched":
+        return batched(args)
+    if args.mode == "served":
+        return served(args)
     import numpy as np
     import torch
 
@@ -163,6 +177,168 @@ def main():
                                "sample": "the full benchmark set (N=2^24): exact kd-tree kNN k=%d "
                                          "(%.1fs) + FoF (%.1fs)" % (k, t1 - t0, t2 - t1),
                                "gpu_matches_oracle": ok}
+    print(json.dumps(out), flush=True)
+
+
+def batched(args):
+    """Many independent clustered sets (N per set log-uniform in [2^10, 2^18]),
+    kNN k=16 + FoF with each set's own b: one forest (one sort and one launch
+    per stage for all sets) against per-set jz_build + jz_knn + jz_fof."""
+    import numpy as np
+    import torch
+
+    from paper_2604_05885_amd import api, inputs
+
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    pts, off, b = inputs.batched_sets(args.sets, seed=4)
+    n = int(off[-1])
+    print("# generated %d sets, %d points in %.1fs" % (args.sets, n, time.time() - t0),
+          file=sys.stderr, flush=True)
+    dev = torch.from_numpy(pts).cuda()
+    k = args.k
+    idx = torch.empty((n, k), dtype=torch.int32, device="cuda")
+    d2 = torch.empty((n, k), dtype=torch.float32, device="cuda")
+    lab = torch.empty(n, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def forest():
+        f = api.jz_forest_build(dev, off, stream=stream)
+        f.knn(k, idx, d2, stream=stream)
+        f.fof(b, lab, stream=stream)
+        st = f.stats()
+        f.free()
+        return st
+
+    for _ in range(args.warmup):
+        forest()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st = forest()
+    torch.cuda.synchronize()
+    t_batched = (time.perf_counter() - t0) / args.steps
+    bi, bd, bl = idx.clone(), d2.clone(), lab.clone()
+
+    def plain(limit=None):
+        for s in range(args.sets if limit is None else limit):
+            a, e = int(off[s]), int(off[s + 1])
+            if e == a:
+                continue
+            t = api.jz_build(dev[a:e], stream=stream)
+            t.knn(k, idx[a:e], d2[a:e], stream=stream)
+            t.fof(float(b[s]), lab[a:e], stream=stream)
+            t.free()
+
+    plain(min(args.sets, 64))  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain()
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    same = bool(torch.equal(bi, idx) and torch.equal(bd.view(torch.int32), d2.view(torch.int32))
+                and torch.equal(bl, lab))
+    out = {
+        "metric": "batched kNN(k=16)+FoF solves/s (sets solved per second)",
+        "value": args.sets / t_batched,
+        "unit": "solves/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": t_batched * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "%d clustered sets, N per set log-uniform in [2^10, 2^18] "
+                               "(total %d points), kNN k=%d + FoF b=fl32(0.2 N_s^-1/3) per set"
+                               % (args.sets, n, k), "sets": args.sets, "points": n},
+        "plain_solves_per_s": args.sets / t_plain,
+        "speedup_vs_plain": t_plain / t_batched,
+        "points_per_s": n / t_batched,
+        "identical_to_plain": same,
+        "forest_stats": {kk: v for kk, v in st.items() if kk in ("planes", "nodes", "super_nodes")},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def served(args):
+    """Open-loop Poisson stream of kNN / FoF requests (k in {8,16,32}, alpha in
+    {0.1,0.2}, N log-uniform in [2^12, 2^22]) through the continuous-batching
+    server, against the same stream through per-request launches (one request
+    per batch, one worker). Latency = completion - scheduled arrival."""
+    import numpy as np
+    import torch
+
+    from paper_2604_05885_amd import api, inputs
+
+    torch.cuda.set_device(0)
+    rng = np.random.default_rng(5)
+    t0 = time.time()
+    pool = []
+    for i in range(args.pool):
+        nn = int(np.floor(2.0 ** rng.uniform(12, 22)))
+        p = inputs.clustered(nn, max(1, int(round(4096 * nn / 2.0 ** 24))), seed=5_000_000 + i)
+        pool.append(torch.from_numpy(p).cuda())
+    outs = [{kk: (torch.empty((q.shape[0], kk), dtype=torch.int32, device="cuda"),
+                  torch.empty((q.shape[0], kk), dtype=torch.float32, device="cuda"))
+             for kk in (8, 16, 32)} for q in pool]
+    labs = [torch.empty(q.shape[0], dtype=torch.int32, device="cuda") for q in pool]
+    torch.cuda.synchronize()
+    print("# pool of %d sets (%d points) in %.1fs" % (args.pool, sum(q.shape[0] for q in pool),
+                                                      time.time() - t0), file=sys.stderr, flush=True)
+    count = int(args.rate * args.duration)
+    reqs = inputs.served_requests(count, seed=5, rate_hz=args.rate)
+    for r in reqs:
+        r["set"] = int(rng.integers(args.pool))
+
+    def run(streams, max_sets):
+        S = api.Server(streams=streams, max_batch_sets=max_sets, hbm_budget=int(200e9))
+        # warm the library (kernels, pool, learned list sizes)
+        for q, o, l in zip(pool[:8], outs[:8], labs[:8]):
+            S.wait(S.submit_knn(q, 16, *o[16]))
+            S.wait(S.submit_fof(q, inputs.linking_length(q.shape[0]), l))
+        t_start = api.now_ns() + int(0.05e9)
+        tickets = []
+        for r in reqs:
+            due = t_start + int(r["t"] * 1e9)
+            while api.now_ns() < due:
+                pass
+            q = pool[r["set"]]
+            if r["op"] == "knn":
+                tk = S.submit_knn(q, r["k"], *outs[r["set"]][r["k"]])
+            else:
+                tk = S.submit_fof(q, inputs.linking_length(q.shape[0], r["alpha"]),
+                                  labs[r["set"]])
+            tickets.append((tk, due, r))
+        lat, last_done, first_due, npts = [], 0, None, 0
+        for tk, due, r in tickets:
+            _, done_ns = S.wait(tk)
+            S.release(tk)
+            if r["t"] >= args.measure_after:
+                lat.append((done_ns - due) / 1e6)
+                last_done = max(last_done, done_ns)
+                first_due = due if first_due is None else min(first_due, due)
+                npts += pool[r["set"]].shape[0]
+        st = S.stats()
+        S.close()
+        lat = np.array(lat)
+        span = (last_done - first_due) / 1e9
+        return {"solves_per_s": len(lat) / span, "points_per_s": npts / span,
+                "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                "requests": len(lat), "batches": st["batches"],
+                "max_batch": st["max_batch_sets_seen"]}
+
+    cont = run(args.streams, 4096)
+    fifo = run(1, 1)
+    out = {
+        "metric": "served kNN/FoF solves/s with p50/p99 latency (open-loop Poisson arrivals)",
+        "value": cont["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+        "steps": len(reqs), "warmup": 0, "ms_per_step": None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "Poisson %g req/s for %gs (first %gs warm-up); each request kNN "
+                               "(k in {8,16,32}) or FoF (alpha in {0.1,0.2}) on one of %d clustered "
+                               "sets with N log-uniform in [2^12, 2^22]; HBM budget 200 GB"
+                               % (args.rate, args.duration, args.measure_after, args.pool)},
+        "continuous_batching": cont,
+        "per_request_fifo": fifo,
+        "speedup_vs_fifo": cont["solves_per_s"] / fifo["solves_per_s"],
+    }
     print(json.dumps(out), flush=True)
 
 

@@ -129,6 +129,79 @@ JZ_API jz_status jz_forest_build(const float *points, const int64_t *offsets, in
  * finite values >= 0). label[n] is set-local (smallest index within the set). */
 JZ_API jz_status jz_forest_fof(jz_tree *t, const float *b, int32_t *label, void *stream);
 
+/* ---- serving: a continuous-batching request loop -----------------------
+ * Requests (kNN or FoF on their own point sets) are submitted at any time from
+ * any thread. Worker threads, each with its own HIP stream, repeatedly take
+ * the oldest pending request and every later pending request of the same
+ * kind (same op, same k), as far as the device-memory budget and the batch
+ * caps allow, solve them as one forest (one sort, one set of launches), and
+ * copy each result to its request's output buffers. Requests that arrive
+ * while batches run join the next batch a worker forms; batches on different
+ * streams overlap on the device. Each result is identical to what
+ * jz_build + jz_knn / jz_fof give for that request alone. */
+typedef struct jz_server jz_server;
+
+enum { JZ_OP_KNN = 0, JZ_OP_FOF = 1 };
+
+typedef struct jz_request {
+    int op;                  /* JZ_OP_KNN or JZ_OP_FOF */
+    int k;                   /* kNN: neighbours per point, [1, 32] */
+    float b;                 /* FoF: linking length, finite, >= 0 */
+    const float *points;     /* DEVICE [n][3]; must stay valid until the request is done */
+    int64_t n;               /* [0, 2^31-2] */
+    int32_t *idx;            /* kNN output, DEVICE [n][k] (input order, indices within the request) */
+    float *dist2;            /* kNN output, DEVICE [n][k] */
+    int32_t *label;          /* FoF output, DEVICE [n] (smallest index within the request's group) */
+} jz_request;
+
+typedef struct jz_server_opts {
+    size_t hbm_budget;       /* device bytes the in-flight batches may use (estimated per
+                                request from n, op and k). Default 200e9. */
+    int streams;             /* worker threads / HIP streams (batches in flight), [1, 16]. Default 4. */
+    int64_t max_batch_points;/* most points per batch. Default 2^26. */
+    int max_batch_sets;      /* most requests per batch, [1, 65536]. Default 4096. */
+    jz_build_opts build;     /* tree options for every batch */
+} jz_server_opts;
+
+JZ_API void jz_server_default_opts(jz_server_opts *o);
+
+/* Start the workers on the current HIP device. */
+JZ_API jz_status jz_server_create(const jz_server_opts *opts, jz_server **out);
+
+/* Queue a request (copied; the buffers it points to are not). *ticket
+ * identifies it. Invalid requests, and requests whose estimated footprint
+ * exceeds the whole budget, are rejected here (JZ_E_INVALID / JZ_E_OOM). */
+JZ_API jz_status jz_server_submit(jz_server *s, const jz_request *r, uint64_t *ticket);
+
+/* *done = 1 once the request's outputs are complete on the device; then
+ * *result holds its status and *done_ns the completion time on the clock of
+ * jz_now_ns(). Any output pointer may be NULL. */
+JZ_API jz_status jz_server_poll(jz_server *s, uint64_t ticket, int *done, jz_status *result,
+                                int64_t *done_ns);
+
+/* Block until the request is done (same outputs as jz_server_poll). */
+JZ_API jz_status jz_server_wait(jz_server *s, uint64_t ticket, jz_status *result,
+                                int64_t *done_ns);
+
+/* Forget a finished ticket (its record is freed). */
+JZ_API jz_status jz_server_release(jz_server *s, uint64_t ticket);
+
+typedef struct jz_serve_stats {
+    int64_t submitted, completed, failed, batches;
+    int64_t points_done;
+    int64_t pending;          /* submitted, not yet in a batch */
+    int64_t in_flight_bytes;  /* budget in use by running batches */
+    int64_t max_batch_sets_seen;
+} jz_serve_stats;
+
+JZ_API jz_status jz_server_stats(jz_server *s, jz_serve_stats *st);
+
+/* Finish every queued and running request, stop the workers, free the server. */
+JZ_API void jz_server_destroy(jz_server *s);
+
+/* Monotonic clock used for completion times (nanoseconds). */
+JZ_API int64_t jz_now_ns(void);
+
 #define JZ_MAX_PLANES 16
 
 typedef struct jz_stats {

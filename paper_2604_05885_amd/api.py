@@ -62,7 +62,34 @@ class Allocator(ctypes.Structure):
                                           ctypes.c_void_p))]
 
 
+class Request(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int), ("k", ctypes.c_int), ("b", ctypes.c_float),
+                ("points", ctypes.c_void_p), ("n", ctypes.c_int64), ("idx", ctypes.c_void_p),
+                ("dist2", ctypes.c_void_p), ("label", ctypes.c_void_p)]
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("streams", ctypes.c_int),
+                ("max_batch_points", ctypes.c_int64), ("max_batch_sets", ctypes.c_int),
+                ("build", BuildOpts)]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("failed", ctypes.c_int64), ("batches", ctypes.c_int64),
+                ("points_done", ctypes.c_int64), ("pending", ctypes.c_int64),
+                ("in_flight_bytes", ctypes.c_int64), ("max_batch_sets_seen", ctypes.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+JZ_OP_KNN, JZ_OP_FOF = 0, 1
+
 _vp = ctypes.c_void_p
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_intp = ctypes.POINTER(ctypes.c_int)
 _SIGS = {
     "jz_default_opts": (None, [ctypes.POINTER(BuildOpts)]),
     "jz_build": (ctypes.c_int, [_vp, ctypes.c_int64, _vp, ctypes.POINTER(BuildOpts),
@@ -80,6 +107,15 @@ _SIGS = {
     "jz_release_cached": (None, []),
     "jz_last_error": (ctypes.c_char_p, []),
     "jz_abi_version": (ctypes.c_int, []),
+    "jz_server_default_opts": (None, [ctypes.POINTER(ServerOpts)]),
+    "jz_server_create": (ctypes.c_int, [ctypes.POINTER(ServerOpts), ctypes.POINTER(_vp)]),
+    "jz_server_submit": (ctypes.c_int, [_vp, ctypes.POINTER(Request), _u64p]),
+    "jz_server_poll": (ctypes.c_int, [_vp, ctypes.c_uint64, _intp, _intp, _i64p]),
+    "jz_server_wait": (ctypes.c_int, [_vp, ctypes.c_uint64, _intp, _i64p]),
+    "jz_server_release": (ctypes.c_int, [_vp, ctypes.c_uint64]),
+    "jz_server_stats": (ctypes.c_int, [_vp, ctypes.POINTER(ServeStats)]),
+    "jz_server_destroy": (None, [_vp]),
+    "jz_now_ns": (ctypes.c_int64, []),
 }
 
 
@@ -284,3 +320,104 @@ def fof(points, b: float, opts: BuildOpts | None = None):
     """Build + FoF in one call; returns labels."""
     with jz_build(points, opts) as t:
         return t.fof(b)
+
+
+def now_ns() -> int:
+    """The library's monotonic clock (ns), the clock of server completion times."""
+    return int(lib.jz_now_ns())
+
+
+class Server:
+    """Continuous-batching request loop (``jz_server_*``).
+
+    ``submit_knn`` / ``submit_fof`` queue a request on CUDA tensors and return
+    a ticket; the tensors are kept alive until the ticket is released.
+    """
+
+    def __init__(self, hbm_budget: int | None = None, streams: int | None = None,
+                 max_batch_points: int | None = None, max_batch_sets: int | None = None,
+                 build: BuildOpts | None = None):
+        o = ServerOpts()
+        lib.jz_server_default_opts(ctypes.byref(o))
+        if hbm_budget is not None:
+            o.hbm_budget = int(hbm_budget)
+        if streams is not None:
+            o.streams = int(streams)
+        if max_batch_points is not None:
+            o.max_batch_points = int(max_batch_points)
+        if max_batch_sets is not None:
+            o.max_batch_sets = int(max_batch_sets)
+        if build is not None:
+            o.build = build
+        h = ctypes.c_void_p()
+        _check(lib.jz_server_create(ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def _submit(self, req: Request, keep) -> int:
+        t = ctypes.c_uint64()
+        _check(lib.jz_server_submit(self._h, ctypes.byref(req), ctypes.byref(t)))
+        self._keep[t.value] = keep
+        return t.value
+
+    def submit_knn(self, points, k: int, idx=None, dist2=None) -> int:
+        import torch
+        p = _points(points)
+        n = p.shape[0]
+        if idx is None:
+            idx = torch.empty((n, k), dtype=torch.int32, device=p.device)
+        if dist2 is None:
+            dist2 = torch.empty((n, k), dtype=torch.float32, device=p.device)
+        r = Request(JZ_OP_KNN, int(k), 0.0, p.data_ptr(), n, idx.data_ptr(), dist2.data_ptr(), None)
+        return self._submit(r, (p, idx, dist2))
+
+    def submit_fof(self, points, b: float, label=None) -> int:
+        import torch
+        p = _points(points)
+        n = p.shape[0]
+        if label is None:
+            label = torch.empty(n, dtype=torch.int32, device=p.device)
+        r = Request(JZ_OP_FOF, 0, float(np.float32(b)), p.data_ptr(), n, None, None,
+                    label.data_ptr())
+        return self._submit(r, (p, label))
+
+    def poll(self, ticket: int):
+        """(done, status, completion time ns)."""
+        d, st, t = ctypes.c_int(), ctypes.c_int(), ctypes.c_int64()
+        _check(lib.jz_server_poll(self._h, ticket, ctypes.byref(d), ctypes.byref(st),
+                                  ctypes.byref(t)))
+        return bool(d.value), st.value, t.value
+
+    def wait(self, ticket: int):
+        """Block until done; returns (outputs tuple, completion time ns)."""
+        st, t = ctypes.c_int(), ctypes.c_int64()
+        _check(lib.jz_server_wait(self._h, ticket, ctypes.byref(st), ctypes.byref(t)))
+        _check(st.value)
+        return self._keep[ticket][1:], t.value
+
+    def release(self, ticket: int):
+        _check(lib.jz_server_release(self._h, ticket))
+        self._keep.pop(ticket, None)
+
+    def stats(self) -> dict:
+        s = ServeStats()
+        _check(lib.jz_server_stats(self._h, ctypes.byref(s)))
+        return s.as_dict()
+
+    def close(self):
+        if self._h:
+            lib.jz_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

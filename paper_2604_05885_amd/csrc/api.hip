@@ -183,6 +183,10 @@ void dev_free(const AllocCtx &a, void *p, size_t bytes, hipStream_t s) {
 
 // ---------------------------------------------------------------------------
 
+jz_status make_tree_impl(const float *points, const int64_t *offsets, int nsets, int64_t n,
+                         void *stream, const jz_build_opts *opts, const jz_allocator *alloc,
+                         jz_tree **out);
+
 namespace {
 
 struct DeviceGuard {
@@ -207,9 +211,16 @@ jz_status check_opts(const jz_build_opts &o) {
     return JZ_OK;
 }
 
-jz_status make_tree(const float *points, const int64_t *offsets, int nsets, int64_t n,
-                    void *stream, const jz_build_opts *opts, const jz_allocator *alloc,
-                    jz_tree **out) {
+}  // namespace
+
+jz_status tree_create(const float *points, const int64_t *offsets, int nsets, hipStream_t s,
+                      const jz_build_opts *opts, const jz_allocator *alloc, jz_tree **out) {
+    return make_tree_impl(points, offsets, nsets, offsets[nsets], (void *)s, opts, alloc, out);
+}
+
+jz_status make_tree_impl(const float *points, const int64_t *offsets, int nsets, int64_t n,
+                         void *stream, const jz_build_opts *opts, const jz_allocator *alloc,
+                         jz_tree **out) {
     if (!out) return jz_fail(JZ_E_INVALID, "out is NULL");
     *out = nullptr;
     if (n < 0 || n > (int64_t)INT32_MAX - 1) return jz_fail(JZ_E_INVALID, "n must be in [0, 2^31-2]");
@@ -258,8 +269,6 @@ jz_status make_tree(const float *points, const int64_t *offsets, int nsets, int6
     return JZ_OK;
 }
 
-}  // namespace
-
 extern "C" {
 
 void jz_default_opts(jz_build_opts *o) {
@@ -278,7 +287,7 @@ jz_status jz_build(const float *points, int64_t n, void *stream, const jz_build_
                    const jz_allocator *alloc, jz_tree **out) {
     g_err.clear();
     const int64_t off[2] = {0, n < 0 ? 0 : n};
-    return make_tree(points, off, 1, n, stream, opts, alloc, out);
+    return make_tree_impl(points, off, 1, n, stream, opts, alloc, out);
 }
 
 jz_status jz_forest_build(const float *points, const int64_t *offsets, int nsets, void *stream,
@@ -290,7 +299,7 @@ jz_status jz_forest_build(const float *points, const int64_t *offsets, int nsets
     if (offsets[0] != 0) return jz_fail(JZ_E_INVALID, "offsets[0] must be 0");
     for (int i = 0; i < nsets; ++i)
         if (offsets[i + 1] < offsets[i]) return jz_fail(JZ_E_INVALID, "offsets must be non-decreasing");
-    return make_tree(points, offsets, nsets, offsets[nsets], stream, opts, alloc, out);
+    return make_tree_impl(points, offsets, nsets, offsets[nsets], stream, opts, alloc, out);
 }
 
 jz_status jz_knn(jz_tree *t, int k, int32_t *idx, float *dist2, void *stream) {

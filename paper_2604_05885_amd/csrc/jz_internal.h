@@ -121,6 +121,10 @@ struct jz_tree {
     jz_stats st{};
 };
 
+// create a tree over nsets sets (offsets: host, nsets + 1); on error *out is NULL
+jz_status tree_create(const float *points, const int64_t *offsets, int nsets, hipStream_t s,
+                      const jz_build_opts *opts, const jz_allocator *alloc, jz_tree **out);
+
 // pipelines (build.hip / knn.hip / fof.hip)
 jz_status build_tree(jz_tree *t, const float *points, hipStream_t s);
 jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s);

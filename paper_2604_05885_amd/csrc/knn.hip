@@ -324,20 +324,59 @@ __device__ __forceinline__ float point_box_low2(const float4 &q, const Node &b) 
     return s + zz;
 }
 
-constexpr int CQ = 8;         // queued candidates per lane between insert rounds
 constexpr int SB = 8;         // source leaves examined per batch
-constexpr int TILE_PTS = 128; // source points staged per batch
+constexpr int TILE_PTS = 128; // source points staged per batch (positions fit a byte)
+constexpr int CQ = 32;        // queued candidate positions per lane
+constexpr int CH = 8;         // tile positions a lane scans between queue checks
 
-// Leaf stage, one wave per receiving leaf (lanes = its query points).
-// Source leaves are taken in r_low order, in batches: the Node records of up to
-// SB sources are read together; each lane marks the sources its query can
-// still reach (point-to-box bound <= its current k-th distance); the points of
-// the sources some lane needs are staged together in one LDS tile; then every
-// lane tests them against its k-th key. The walk stops at the first source
-// whose r_low exceeds every lane's k-th distance. Accepted candidates are
-// queued in LDS (CQ per lane) and inserted into the register top-k in rounds,
-// so insert time follows the busiest lane rather than every accepted
-// candidate of any lane.
+constexpr int next_pow2(int k) {
+    int m = 1;
+    while (m < k) m <<= 1;
+    return m;
+}
+
+// Keep the K smallest of two ascending key lists a and b in a (ascending).
+// With both lists padded to M = next power of two, min(a[i], b[M-1-i]) is a
+// bitonic sequence holding the M smallest of the padded union (so the K
+// smallest of a and b); a bitonic sorter then orders it.
+template <int K>
+__device__ __forceinline__ void merge_topk(uint64_t (&a)[K], const uint64_t (&b)[K]) {
+    constexpr int M = next_pow2(K);
+    uint64_t c[M];
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+        const uint64_t x = i < K ? a[i] : PAD_KEY;
+        const uint64_t y = (M - 1 - i) < K ? b[M - 1 - i] : PAD_KEY;
+        c[i] = x < y ? x : y;
+    }
+#pragma unroll
+    for (int d = M / 2; d > 0; d >>= 1) {
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+            if ((i & d) == 0) {
+                const uint64_t x = c[i], y = c[i + d];
+                c[i] = x < y ? x : y;
+                c[i + d] = x < y ? y : x;
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < K; ++i) a[i] = c[i];
+}
+
+// Leaf stage, one wave per receiving leaf. A leaf of at most 16 (32) points
+// gives each query 4 (2) lanes; the lanes of a query scan interleaved slices
+// of every staged tile, keep their own top-k, and prune with the smallest
+// k-th distance of the group (the merged k-th can only be smaller), and their
+// lists are merged at the end.
+// Source leaves are taken in r_low order, in batches: the Node records of up
+// to SB sources are read together; each lane marks the sources its query can
+// still reach (point-to-box bound <= the group's k-th distance); the points of
+// the sources some lane needs are staged together in one LDS tile. The walk
+// stops at the first source whose r_low exceeds every query's k-th distance.
+// Candidates within the k-th distance are queued as tile positions and
+// inserted into the register top-k in rounds, so insert time follows the
+// busiest lane rather than every accepted candidate of any lane.
 template <int K>
 __global__ __launch_bounds__(256) void k_leaf_knn(
     const int2 *__restrict__ seg, const int2 *__restrict__ list, const Node *__restrict__ leaves,
@@ -348,13 +387,16 @@ __global__ __launch_bounds__(256) void k_leaf_knn(
     __shared__ float4 s_tile[4][TILE_PTS];
     __shared__ Node s_nodes[4][SB];
     __shared__ int s_offs[4][SB + 1];
-    __shared__ uint64_t s_q[4][CQ][64];
+    __shared__ uint8_t s_q[4][CQ][64];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int A = xcd_block(blockIdx.x, gridDim.x) * 4 + w;
     if (A >= n_leaves) return;
     const Node a = leaves[A];
-    const bool act = lane < a.count;
-    const float4 me = pts[a.start + (act ? lane : 0)];
+    const int lgS = a.count <= 16 ? 2 : (a.count <= 32 ? 1 : 0);  // log2 lanes per query
+    const int S = 1 << lgS;
+    const int q = lane & ((64 >> lgS) - 1), h = lane >> (6 - lgS);
+    const bool act = q < a.count;
+    const float4 me = pts[a.start + (act ? q : 0)];
     const int2 sg = seg[A];
     const int2 *gl = list + sg.x;
     const int len = sg.y;
@@ -369,25 +411,41 @@ __global__ __launch_bounds__(256) void k_leaf_knn(
 #pragma unroll
     for (int i = 0; i < K; ++i) best[i] = PAD_KEY;
     unsigned evals = 0, visited = 0;
+    int qn = 0;  // queued positions of this lane
+
+    // insert the queued candidates of every lane into its top-k
+    auto drain = [&]() {
+        for (int c = 0; __ballot(c < qn); ++c) {
+            if (c < qn) {
+                const float4 s = tile[s_q[w][c][lane]];
+                const float dd = dist2_pts(me.x, me.y, me.z, s.x, s.y, s.z);
+                const uint64_t key =
+                    ((uint64_t)__float_as_uint(dd) << 32) | (uint32_t)__float_as_int(s.w);
+                if (key < best[K - 1]) topk_insert<K>(best, key);
+            }
+        }
+        qn = 0;
+    };
+
     int t = 0;
     while (t < len) {
-        const float kth = __uint_as_float((uint32_t)(best[K - 1] >> 32));
+        float kth = __uint_as_float((uint32_t)(best[K - 1] >> 32));
+        if (lgS >= 1) kth = fminf(kth, __shfl_xor(kth, 32, 64));
+        if (lgS >= 2) kth = fminf(kth, __shfl_xor(kth, 16, 64));
         const float Rw = wave_max(act ? kth : -INFINITY);
         // sources t .. t + nb_n - 1 of this batch (all with r_low <= Rw)
         int src = 0;
         float rl = INFINITY;
         if (lane < SB && t + lane < len) list_entry(staged, L, gl, t + lane, src, rl);
         const bool inb = lane < SB && t + lane < len && (!staged || rl <= Rw);
-        const uint64_t inmask = __ballot(inb);
-        // sources are sorted by r_low: the batch is a prefix; an empty one ends the walk
+        const uint64_t inmask = __ballot(inb);  // a prefix of lanes 0..SB-1 (sorted)
         const int nb_n = __ffsll((unsigned long long)(~inmask)) - 1;
         if (nb_n == 0) break;
         if (lane < nb_n) nb[lane] = leaves[src];
         wave_lds_sync();
-        // per-lane need bits; which sources any lane needs
         unsigned needbits = 0;
-        for (int q = 0; q < nb_n; ++q)
-            if (act && point_box_low2(me, nb[q]) <= kth) needbits |= 1u << q;
+        for (int qq = 0; qq < nb_n; ++qq)
+            if (act && point_box_low2(me, nb[qq]) <= kth) needbits |= 1u << qq;
         unsigned any = needbits;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) any |= __shfl_xor(any, o, 64);
@@ -395,53 +453,54 @@ __global__ __launch_bounds__(256) void k_leaf_knn(
         // (every lane computes the same offsets; lane 0 keeps them in LDS)
         int take = 0, npts = 0;
         if (lane == 0) offs[0] = 0;
-        for (int q = 0; q < nb_n; ++q) {
-            const int c = (any >> q) & 1u ? nb[q].count : 0;
+        for (int qq = 0; qq < nb_n; ++qq) {
+            const int c = (any >> qq) & 1u ? nb[qq].count : 0;
             if (npts + c > TILE_PTS) break;
             npts += c;
-            if (lane == 0) offs[q + 1] = npts;
-            take = q + 1;
+            if (lane == 0) offs[qq + 1] = npts;
+            take = qq + 1;
         }
         wave_lds_sync();
-        // stage the points of the taken sources
         for (int f = lane; f < npts; f += 64) {
-            int q = 0;
-            while (offs[q + 1] <= f) ++q;
-            tile[f] = pts[nb[q].start + (f - offs[q])];
+            int qq = 0;
+            while (offs[qq + 1] <= f) ++qq;
+            tile[f] = pts[nb[qq].start + (f - offs[qq])];
         }
         wave_lds_sync();
-        const uint64_t thr = best[K - 1];
-        int qn = 0;
-        for (int q = 0; q < take; ++q) {
-            if (!((any >> q) & 1u)) continue;
+        for (int qq = 0; qq < take; ++qq) {
+            if (!((any >> qq) & 1u)) continue;
             ++visited;
-            const bool need = (needbits >> q) & 1u;
-            const int f0 = offs[q], f1 = offs[q + 1];
-            for (int j0 = f0; j0 < f1; j0 += CQ) {
-                const int j1 = min(f1, j0 + CQ);
-                for (int j = j0; j < j1; ++j) {
+            const bool need = (needbits >> qq) & 1u;
+            const int f0 = offs[qq], f1 = offs[qq + 1];
+            for (int j0 = f0; j0 < f1; j0 += CH * S) {
+                const int j1 = min(f1, j0 + CH * S);
+                for (int j = j0 + h; j < j1; j += S) {
                     const float4 s = tile[j];
                     const float dd = dist2_pts(me.x, me.y, me.z, s.x, s.y, s.z);
-                    const uint64_t key =
-                        ((uint64_t)__float_as_uint(dd) << 32) | (uint32_t)__float_as_int(s.w);
-                    if (need && key < thr) s_q[w][qn++][lane] = key;
+                    if (need && dd <= kth) s_q[w][qn++][lane] = (uint8_t)j;
                 }
-                if (__ballot(qn > 0)) {
-                    for (int c = 0; __ballot(c < qn); ++c) {
-                        if (c < qn) {
-                            const uint64_t key = s_q[w][c][lane];
-                            if (key < best[K - 1]) topk_insert<K>(best, key);
-                        }
-                    }
-                    qn = 0;
-                }
+                if (__ballot(qn > CQ - CH)) drain();
             }
-            evals += need ? (unsigned)(f1 - f0) : 0u;
+            if (need) evals += (unsigned)((f1 - f0 - h + S - 1) >> lgS);
         }
+        drain();
         wave_lds_sync();
         t += take;
     }
-    if (act) {
+    // merge the partial lists of a query's lanes
+    if (lgS >= 1) {
+        uint64_t other[K];
+#pragma unroll
+        for (int i = 0; i < K; ++i) other[i] = __shfl_xor(best[i], 32, 64);
+        merge_topk<K>(best, other);
+    }
+    if (lgS >= 2) {
+        uint64_t other[K];
+#pragma unroll
+        for (int i = 0; i < K; ++i) other[i] = __shfl_xor(best[i], 16, 64);
+        merge_topk<K>(best, other);
+    }
+    if (act && h == 0) {
         const int64_t row = (int64_t)__float_as_int(me.w);
         const int base = leaf_base ? leaf_base[A] : 0;
         int32_t *oi = out_idx + row * K;

@@ -1,0 +1,93 @@
+"""GPU tests of the continuous-batching server (through the C ABI): every
+request's result equals its standalone result and the oracle, whatever batch
+it ran in."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2604_05885_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def jz():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2604_05885_amd import api
+    return api
+
+
+def make_requests(seed=3):
+    rng = np.random.default_rng(seed)
+    sizes = [0, 1, 7, 300, 5000, 20000, 48, 1000, 3000, 65, 12000, 2, 700]
+    reqs = []
+    for i, n in enumerate(sizes):
+        p = inputs.clustered(n, max(1, n // 800), seed=1000 + i) if n else np.zeros((0, 3), np.float32)
+        if i % 3 == 2:
+            reqs.append(("fof", p, float(inputs.linking_length(max(n, 1), rng.uniform(0.1, 0.6)))))
+        else:
+            reqs.append(("knn", p, int(rng.choice([8, 16]))))
+    return reqs
+
+
+def standalone(jz, op, p, arg):
+    with jz.jz_build(torch.from_numpy(p).cuda()) as t:
+        if op == "knn":
+            i, d = t.knn(arg)
+            torch.cuda.synchronize()
+            return i.cpu().numpy(), d.cpu().numpy()
+        lab = t.fof(arg)
+        torch.cuda.synchronize()
+        return (lab.cpu().numpy(),)
+
+
+@pytest.mark.parametrize("streams,max_sets", [(3, 4), (1, 4096), (4, 1)])
+def test_server_results_equal_standalone(jz, streams, max_sets):
+    reqs = make_requests()
+    dev = [torch.from_numpy(p).cuda() for _, p, _ in reqs]
+    torch.cuda.synchronize()
+    with jz.Server(streams=streams, max_batch_sets=max_sets) as S:
+        tickets = []
+        for (op, p, arg), d in zip(reqs, dev):
+            tickets.append(S.submit_knn(d, arg) if op == "knn" else S.submit_fof(d, arg))
+        outs = []
+        for t in tickets:
+            o, _ = S.wait(t)
+            outs.append(tuple(x.cpu().numpy() for x in o))
+            S.release(t)
+        st = S.stats()
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    if max_sets > 1 and streams == 1:
+        assert st["batches"] < len(reqs)  # requests were batched
+    for (op, p, arg), got in zip(reqs, outs):
+        want = standalone(jz, op, p, arg)
+        for g, w in zip(got, want):
+            assert np.array_equal(g.view(np.uint32) if g.dtype == np.float32 else g,
+                                  w.view(np.uint32) if w.dtype == np.float32 else w)
+        if op == "knn":
+            oi, od = oracle.knn_bf(p, arg) if p.shape[0] else (np.zeros((0, arg), np.int32),) * 2
+            assert np.array_equal(got[0], oi)
+        else:
+            assert np.array_equal(got[0], oracle.fof_bf(p, arg))
+
+
+def test_server_budget(jz):
+    p = torch.from_numpy(inputs.uniform(4000, 8)).cuda()
+    torch.cuda.synchronize()
+    # a budget that admits one request at a time still completes everything
+    with jz.Server(hbm_budget=8_000_000, streams=2) as S:
+        ts = [S.submit_knn(p, 8) for _ in range(5)]
+        res = [S.wait(t)[0] for t in ts]
+        for r in res[1:]:
+            assert torch.equal(r[0], res[0][0]) and torch.equal(r[1], res[0][1])
+    # a request larger than the whole budget is rejected at submit
+    with jz.Server(hbm_budget=1_000_000) as S:
+        with pytest.raises(jz.JzError) as e:
+            S.submit_knn(p, 8)
+        assert e.value.status == jz.JZ_E_OOM
+        with pytest.raises(jz.JzError) as e:
+            S.submit_knn(p, 40)
+        assert e.value.status == jz.JZ_E_UNSUPPORTED
