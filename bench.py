@@ -202,8 +202,13 @@ def batched(args):
     lab = torch.empty(n, dtype=torch.int32, device="cuda")
     stream = torch.cuda.current_stream()
 
+    t0 = time.time()
+    opts, tuned_ms = api.jz_autotune(dev, off, k=k, b=b, stream=stream)
+    print("# autotuned leaf_max=%d coarsen=%d (%.1f ms) in %.1fs" % (
+        opts.leaf_max, opts.coarsen, tuned_ms, time.time() - t0), file=sys.stderr, flush=True)
+
     def forest():
-        f = api.jz_forest_build(dev, off, stream=stream)
+        f = api.jz_forest_build(dev, off, opts, stream=stream)
         f.knn(k, idx, d2, stream=stream)
         f.fof(b, lab, stream=stream)
         st = f.stats()
@@ -253,6 +258,7 @@ def batched(args):
         "points_per_s": n / t_batched,
         "identical_to_plain": same,
         "forest_stats": {kk: v for kk, v in st.items() if kk in ("planes", "nodes", "super_nodes")},
+        "autotuned": {"leaf_max": opts.leaf_max, "coarsen": opts.coarsen},
     }
     print(json.dumps(out), flush=True)
 

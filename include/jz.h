@@ -129,6 +129,21 @@ JZ_API jz_status jz_forest_build(const float *points, const int64_t *offsets, in
  * finite values >= 0). label[n] is set-local (smallest index within the set). */
 JZ_API jz_status jz_forest_fof(jz_tree *t, const float *b, int32_t *label, void *stream);
 
+/* ---- autotuning -----------------------------------------------------------
+ * Time the build plus the requested operations on the caller's workload for
+ * each candidate setting (leaf_max in {32, 48, 64} x coarsen in {4, 8}; other
+ * fields taken from *base or the defaults) and return the fastest in *best
+ * and its time (ms, best of two runs) in *best_ms. points / offsets / nsets
+ * as for jz_forest_build (offsets may be NULL for one set of n points; then
+ * nsets is n). k in [1, 32] runs kNN, k = 0 skips it; b (HOST, one value per
+ * set) runs FoF, NULL skips it. The winner is remembered for the signature
+ * (k, FoF or not, number of sets, log2 of the point count) for the rest of
+ * the process, and later calls with that signature return it without
+ * timing. Results of the method never depend on these options. */
+JZ_API jz_status jz_autotune(const float *points, const int64_t *offsets, int64_t nsets,
+                             int k, const float *b, void *stream, const jz_build_opts *base,
+                             jz_build_opts *best, double *best_ms);
+
 /* ---- serving: a continuous-batching request loop -----------------------
  * Requests (kNN or FoF on their own point sets) are submitted at any time from
  * any thread. Worker threads, each with its own HIP stream, repeatedly take

@@ -116,6 +116,9 @@ _SIGS = {
     "jz_server_stats": (ctypes.c_int, [_vp, ctypes.POINTER(ServeStats)]),
     "jz_server_destroy": (None, [_vp]),
     "jz_now_ns": (ctypes.c_int64, []),
+    "jz_autotune": (ctypes.c_int, [_vp, _i64p, ctypes.c_int64, ctypes.c_int,
+                                   ctypes.POINTER(ctypes.c_float), _vp, ctypes.POINTER(BuildOpts),
+                                   ctypes.POINTER(BuildOpts), ctypes.POINTER(ctypes.c_double)]),
 }
 
 
@@ -320,6 +323,28 @@ def fof(points, b: float, opts: BuildOpts | None = None):
     """Build + FoF in one call; returns labels."""
     with jz_build(points, opts) as t:
         return t.fof(b)
+
+
+def jz_autotune(points, offsets=None, k: int = 16, b=None, base: BuildOpts | None = None,
+                stream=None):
+    """Fastest build options for this workload: (BuildOpts, ms)."""
+    p = _points(points)
+    best = BuildOpts()
+    ms = ctypes.c_double()
+    if offsets is not None:
+        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        offp, nsets = off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), len(off) - 1
+    else:
+        off, offp, nsets = None, None, p.shape[0]
+    bb = None
+    if b is not None:
+        bb = np.ascontiguousarray(np.atleast_1d(b), dtype=np.float32)
+    _check(lib.jz_autotune(ctypes.c_void_p(p.data_ptr()), offp, nsets, int(k),
+                           bb.ctypes.data_as(ctypes.POINTER(ctypes.c_float)) if bb is not None
+                           else None, _stream(stream),
+                           ctypes.byref(base) if base is not None else None,
+                           ctypes.byref(best), ctypes.byref(ms)))
+    return best, ms.value
 
 
 def now_ns() -> int:

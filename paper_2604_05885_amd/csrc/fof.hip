@@ -168,16 +168,36 @@ __global__ __launch_bounds__(256) void k_fof_step(
     }
 }
 
-// Leaf stage: one wave per receiving leaf, lanes over its points. Roots are
-// cached (a lane's own root, and the source points' roots per tile): equal
-// cached roots mean the two points were already connected, since groups only
-// ever merge.
+constexpr int FSB = 8;          // source leaves per batch
+constexpr int FTILE = 128;      // source points staged per batch
+
+__device__ __forceinline__ float point_box_low2_f(const float4 &q, const Node &b) {
+    const float gx = fmaxf(fmaxf(b.lo[0] - q.x, q.x - b.hi[0]), 0.0f);
+    const float gy = fmaxf(fmaxf(b.lo[1] - q.y, q.y - b.hi[1]), 0.0f);
+    const float gz = fmaxf(fmaxf(b.lo[2] - q.z, q.z - b.hi[2]), 0.0f);
+    const float xx = gx * gx;
+    const float yy = gy * gy;
+    const float zz = gz * gz;
+    const float s = xx + yy;
+    return s + zz;
+}
+
+// Leaf stage: one wave per receiving leaf A, lanes over its points. Sources
+// (leaves B >= A) are read in batches of FSB Node records. A source is
+// skipped when A and B are both whole and already one group; a lane skips a
+// source its point cannot reach (point-to-box bound > b^2); the points of the
+// sources some lane needs are staged together in LDS. Roots are looked up
+// only for point pairs that link: a union is needed only when the two roots
+// differ (a lane's own root is cached; groups only ever merge, so equal
+// roots, even looked up at different times, mean already connected). Two
+// whole leaves need only one link.
 __global__ __launch_bounds__(256) void k_leaf_fof(
     const int2 *__restrict__ seg, const int2 *__restrict__ list, const Node *__restrict__ leaves,
     const float4 *__restrict__ pts, int n_leaves, float b2, const float *__restrict__ b2n,
     const int *__restrict__ whole, int *__restrict__ uf, unsigned long long *__restrict__ stats) {
-    __shared__ float4 s_tile[4][64];
-    __shared__ int s_root[4][64];
+    __shared__ float4 s_tile[4][FTILE];
+    __shared__ Node s_nodes[4][FSB];
+    __shared__ int s_offs[4][FSB + 1];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int A = xcd_block(blockIdx.x, gridDim.x) * 4 + w;
     if (A >= n_leaves) return;
@@ -191,40 +211,74 @@ __global__ __launch_bounds__(256) void k_leaf_fof(
     const int2 *gl = list + sg.x;
     const int len = sg.y;
     float4 *tile = s_tile[w];
-    int *rootB = s_root[w];
-    int ra = act ? uf_find(uf, my) : -1;
+    Node *nb = s_nodes[w];
+    int *offs = s_offs[w];
+    int ra = -1;  // cached root of this lane's point
     unsigned evals = 0;
-    for (int t = 0; t < len; ++t) {
-        const int B = gl[t].x;
-        const Node b = leaves[B];
-        const int wB = whole[B];
-        if (wA && wB && uf_find(uf, a.start) == uf_find(uf, b.start)) continue;
-        // b.count <= 64 (leaf_max <= 64)
-        if (lane < b.count) {
-            tile[lane] = pts[b.start + lane];
-            rootB[lane] = wB ? -2 : uf_find(uf, b.start + lane);
+    for (int t = 0; t < len;) {
+        const int nb_n = min(FSB, len - t);
+        const int rA = wA ? uf_find(uf, a.start) : -1;
+        bool skip = false;
+        int wB = 0;
+        if (lane < nb_n) {
+            const int B = gl[t + lane].x;
+            const Node b = leaves[B];
+            nb[lane] = b;
+            wB = whole[B];
+            skip = wA && wB && uf_find(uf, b.start) == rA;
         }
-        const int rB = wB ? uf_find(uf, b.start) : -2;
+        const unsigned skipmask = (unsigned)__ballot(skip);
+        const unsigned wholemask = (unsigned)__ballot(lane < nb_n && wB);
         wave_lds_sync();
-        for (int j = 0; j < b.count; ++j) {
-            const int sj = b.start + j;
-            bool link = false;
-            if (act && sj > my) {
-                const float4 s = tile[j];
-                ++evals;
-                if (dist2_pts(me.x, me.y, me.z, s.x, s.y, s.z) <= bb) {
-                    const int rj = wB ? rB : rootB[j];
-                    if (rj != ra) {
-                        uf_union(uf, my, sj);
-                        ra = uf_find(uf, my);
+        unsigned needbits = 0;
+        for (int q = 0; q < nb_n; ++q)
+            if (!((skipmask >> q) & 1u) && act && point_box_low2_f(me, nb[q]) <= bb)
+                needbits |= 1u << q;
+        unsigned any = needbits;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) any |= __shfl_xor(any, o, 64);
+        int take = 0, npts = 0;
+        if (lane == 0) offs[0] = 0;
+        for (int q = 0; q < nb_n; ++q) {
+            const int c = (any >> q) & 1u ? nb[q].count : 0;
+            if (npts + c > FTILE) break;
+            npts += c;
+            if (lane == 0) offs[q + 1] = npts;
+            take = q + 1;
+        }
+        wave_lds_sync();
+        for (int f = lane; f < npts; f += 64) {
+            int q = 0;
+            while (offs[q + 1] <= f) ++q;
+            tile[f] = pts[nb[q].start + (f - offs[q])];
+        }
+        wave_lds_sync();
+        for (int q = 0; q < take; ++q) {
+            if (!((any >> q) & 1u)) continue;
+            const bool need = (needbits >> q) & 1u;
+            const bool both_whole = wA && ((wholemask >> q) & 1u);
+            const int f0 = offs[q], f1 = offs[q + 1];
+            const int s0 = nb[q].start - f0;  // point index of tile position f
+            for (int f = f0; f < f1; ++f) {
+                const int sj = s0 + f;
+                bool link = false;
+                if (need && sj > my) {
+                    const float4 s = tile[f];
+                    ++evals;
+                    if (dist2_pts(me.x, me.y, me.z, s.x, s.y, s.z) <= bb) {
+                        link = true;
+                        if (ra < 0) ra = uf_find(uf, my);
+                        if (uf_find(uf, sj) != ra) {
+                            uf_union(uf, my, sj);
+                            ra = uf_find(uf, my);
+                        }
                     }
-                    link = true;
                 }
+                if (both_whole && __ballot(link)) break;
             }
-            // two whole leaves need a single link
-            if (wA && wB && __ballot(link)) break;
         }
         wave_lds_sync();
+        t += take;
     }
     const int ev = wave_sum((int)evals);
     if (lane == 0) atomicAdd(stats, (unsigned long long)ev);

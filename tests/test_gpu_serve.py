@@ -91,3 +91,20 @@ def test_server_budget(jz):
         with pytest.raises(jz.JzError) as e:
             S.submit_knn(p, 40)
         assert e.value.status == jz.JZ_E_UNSUPPORTED
+
+
+def test_autotune_picks_valid_options(jz):
+    p = inputs.clustered(30000, 16, 77)
+    d = torch.from_numpy(p).cuda()
+    b = inputs.linking_length(30000)
+    opts, ms = jz.jz_autotune(d, k=8, b=b)
+    assert opts.leaf_max in (32, 48, 64) and opts.coarsen in (4, 8) and ms > 0
+    again, ms2 = jz.jz_autotune(d, k=8, b=b)  # remembered
+    assert (again.leaf_max, again.coarsen, ms2) == (opts.leaf_max, opts.coarsen, ms)
+    with jz.jz_build(d, opts) as t:
+        i, dd = t.knn(8)
+        lab = t.fof(b)
+        torch.cuda.synchronize()
+        wi, wd = oracle.knn_bf(p, 8)
+        assert np.array_equal(i.cpu().numpy(), wi) and np.array_equal(dd.cpu().numpy(), wd)
+        assert np.array_equal(lab.cpu().numpy(), oracle.fof_bf(p, b))
