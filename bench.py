@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "leaf_knn_traffic.json"),
                     help="HBM bytes per launch of the dominant kernel from rocprofv3 counters")
-    ap.add_argument("--mode", choices=["step", "batched", "served"], default="step",
+    ap.add_argument("--mode", choices=["step", "batched", "served", "copycal"], default="step",
                     help="step: N=2^24 kNN+FoF (default); batched: many sets in one forest vs "
                          "per-set launches; served: Poisson request stream")
     ap.add_argument("--sets", type=int, default=4096, help="batched: number of sets")
@@ -68,6 +68,8 @@ def main():
         return batched(args)
     if args.mode == "served":
         return served(args)
+    if args.mode == "copycal":
+        return copycal(args)
     import numpy as np
     import torch
 
@@ -129,7 +131,8 @@ def main():
     if os.path.exists(args.traffic_json):
         with open(args.traffic_json) as f:
             tj = json.load(f)
-        if tj.get("workload") == "clustered-2^24-k16" and tj.get("kernel_hash") is not None:
+        # counters count only while the kernel source they were taken on is unchanged
+        if tj.get("workload") == "clustered-2^24-k16" and tj.get("kernel_hash") == kernel_hash():
             traffic = tj.get("bytes_per_launch")
 
     value = n * args.steps / elapsed
@@ -178,6 +181,27 @@ def main():
                                          "(%.1fs) + FoF (%.1fs)" % (k, t1 - t0, t2 - t1),
                                "gpu_matches_oracle": ok}
     print(json.dumps(out), flush=True)
+
+
+def kernel_hash() -> str:
+    """sha256 of the leaf-kNN source file (ties traffic counters to a kernel version)."""
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2604_05885_amd", "csrc", "knn.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def copycal(args):
+    """Plain device copy of a known size, for scaling rocprofv3 FETCH_SIZE /
+    WRITE_SIZE readings to bytes (run under rocprofv3 --pmc)."""
+    import torch
+    nbytes = 1 << 30
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": "copycal", "bytes_read_per_copy": nbytes,
+                      "bytes_written_per_copy": nbytes, "copies": 3}), flush=True)
 
 
 def batched(args):

@@ -232,6 +232,8 @@ typedef struct jz_stats {
     double leaf_ms;                  /* leaf-stage kernel time (ms), when profiling is on */
     double total_ms;                 /* whole call, device time (ms), when profiling is on */
     int reruns;                      /* capacity reruns in the last call */
+    int64_t insert_rounds;           /* kNN leaf stage: wave-level top-k insert rounds */
+    int64_t tile_steps;              /* kNN leaf stage: wave-level candidate steps */
 } jz_stats;
 
 /* Statistics of the tree and of its last kNN / FoF call. */

@@ -42,7 +42,8 @@ class Stats(ctypes.Structure):
                 ("list_entries", ctypes.c_int64 * (MAX_PLANES + 1)),
                 ("leaf_pairs", ctypes.c_int64), ("leaf_pairs_visited", ctypes.c_int64),
                 ("evaluations", ctypes.c_double), ("leaf_ms", ctypes.c_double),
-                ("total_ms", ctypes.c_double), ("reruns", ctypes.c_int)]
+                ("total_ms", ctypes.c_double), ("reruns", ctypes.c_int),
+                ("insert_rounds", ctypes.c_int64), ("tile_steps", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         P = self.planes
@@ -51,7 +52,8 @@ class Stats(ctypes.Structure):
                 "list_entries": list(self.list_entries[:P]),
                 "leaf_pairs": self.leaf_pairs, "leaf_pairs_visited": self.leaf_pairs_visited,
                 "evaluations": self.evaluations, "leaf_ms": self.leaf_ms,
-                "total_ms": self.total_ms, "reruns": self.reruns}
+                "total_ms": self.total_ms, "reruns": self.reruns,
+                "insert_rounds": self.insert_rounds, "tile_steps": self.tile_steps}
 
 
 class Allocator(ctypes.Structure):

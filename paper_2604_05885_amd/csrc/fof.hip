@@ -186,11 +186,12 @@ __device__ __forceinline__ float point_box_low2_f(const float4 &q, const Node &b
 // (leaves B >= A) are read in batches of FSB Node records. A source is
 // skipped when A and B are both whole and already one group; a lane skips a
 // source its point cannot reach (point-to-box bound > b^2); the points of the
-// sources some lane needs are staged together in LDS. Roots are looked up
-// only for point pairs that link: a union is needed only when the two roots
-// differ (a lane's own root is cached; groups only ever merge, so equal
-// roots, even looked up at different times, mean already connected). Two
-// whole leaves need only one link.
+// sources some lane needs are staged together in LDS. Per source, every lane
+// first records which of its points link to its own point (no atomics);
+// only if some lane links are the roots of the source's points looked up, in
+// parallel, and unions made where the roots differ (a lane's own root is
+// cached; groups only ever merge, so equal roots, even looked up at different
+// times, mean already connected). Two whole leaves need only one link.
 __global__ __launch_bounds__(256) void k_leaf_fof(
     const int2 *__restrict__ seg, const int2 *__restrict__ list, const Node *__restrict__ leaves,
     const float4 *__restrict__ pts, int n_leaves, float b2, const float *__restrict__ b2n,
@@ -198,6 +199,7 @@ __global__ __launch_bounds__(256) void k_leaf_fof(
     __shared__ float4 s_tile[4][FTILE];
     __shared__ Node s_nodes[4][FSB];
     __shared__ int s_offs[4][FSB + 1];
+    __shared__ int s_root[4][64];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int A = xcd_block(blockIdx.x, gridDim.x) * 4 + w;
     if (A >= n_leaves) return;
@@ -213,6 +215,7 @@ __global__ __launch_bounds__(256) void k_leaf_fof(
     float4 *tile = s_tile[w];
     Node *nb = s_nodes[w];
     int *offs = s_offs[w];
+    int *rootT = s_root[w];
     int ra = -1;  // cached root of this lane's point
     unsigned evals = 0;
     for (int t = 0; t < len;) {
@@ -256,26 +259,49 @@ __global__ __launch_bounds__(256) void k_leaf_fof(
         for (int q = 0; q < take; ++q) {
             if (!((any >> q) & 1u)) continue;
             const bool need = (needbits >> q) & 1u;
-            const bool both_whole = wA && ((wholemask >> q) & 1u);
+            const bool wB = (wholemask >> q) & 1u;
             const int f0 = offs[q], f1 = offs[q + 1];
-            const int s0 = nb[q].start - f0;  // point index of tile position f
-            for (int f = f0; f < f1; ++f) {
-                const int sj = s0 + f;
-                bool link = false;
-                if (need && sj > my) {
+            const int b0 = nb[q].start;
+            // 1: which points of this source link to this lane's point
+            uint64_t lm = 0;
+            if (need) {
+                for (int f = f0; f < f1; ++f) {
                     const float4 s = tile[f];
-                    ++evals;
-                    if (dist2_pts(me.x, me.y, me.z, s.x, s.y, s.z) <= bb) {
-                        link = true;
-                        if (ra < 0) ra = uf_find(uf, my);
-                        if (uf_find(uf, sj) != ra) {
-                            uf_union(uf, my, sj);
-                            ra = uf_find(uf, my);
-                        }
+                    if (b0 + (f - f0) > my && dist2_pts(me.x, me.y, me.z, s.x, s.y, s.z) <= bb)
+                        lm |= 1ull << (f - f0);
+                }
+                evals += (unsigned)(f1 - f0);
+            }
+            const uint64_t linking = __ballot(lm != 0);
+            if (!linking) continue;
+            if (wA && wB) {
+                // both leaves are whole: a single link joins them
+                const int leader = __ffsll((unsigned long long)linking) - 1;
+                if (lane == leader) uf_union(uf, my, b0 + __ffsll((unsigned long long)lm) - 1);
+                continue;
+            }
+            // 2: roots of the source's points, looked up in parallel
+            int rB = -1;
+            if (wB) {
+                rB = uf_find(uf, b0);
+            } else if (lane < f1 - f0) {
+                rootT[lane] = uf_find(uf, b0 + lane);
+            }
+            wave_lds_sync();
+            // 3: unite where the roots differ
+            if (lm) {
+                if (ra < 0) ra = uf_find(uf, my);
+                while (lm) {
+                    const int f = __ffsll((unsigned long long)lm) - 1;
+                    lm &= lm - 1;
+                    const int rj = wB ? rB : rootT[f];
+                    if (rj != ra) {
+                        uf_union(uf, my, b0 + f);
+                        ra = uf_find(uf, my);
                     }
                 }
-                if (both_whole && __ballot(link)) break;
             }
+            wave_lds_sync();
         }
         wave_lds_sync();
         t += take;
@@ -348,6 +374,7 @@ jz_status run_fof(jz_tree *t, const float *b2_set_host, int32_t *label, hipStrea
     t->st.evaluations = 0;
     t->st.leaf_ms = t->st.total_ms = 0;
     t->st.reruns = 0;
+    t->st.insert_rounds = t->st.tile_steps = 0;
     if (n == 0) return JZ_OK;
 
     const bool sets = t->nsets > 1;

@@ -66,6 +66,18 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
     return (lane_id() == 0) ? 0ull : (~0ull >> (64 - lane_id()));
 }
 
+// A value that every active lane of the wave holds, moved to a scalar
+// register. The compiler cannot tell that values read from LDS, reduced with
+// shuffles or derived from threadIdx.x / 64 are wave-uniform; marking them
+// gives scalar loop control, scalar loads and fewer vector instructions.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ unsigned uni(unsigned v) {
+    return (unsigned)__builtin_amdgcn_readfirstlane((int)v);
+}
+__device__ __forceinline__ float uni(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
 __device__ __forceinline__ float wave_max(float v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));

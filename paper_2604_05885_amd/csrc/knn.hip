@@ -302,13 +302,32 @@ __global__ __launch_bounds__(256) void k_knn_step(
     }
 }
 
+// Top-k keys are (dist2 bits << 32 | index). dist2 >= 0 is never NaN, so the
+// key's top 12 bits are never 0x7FF and, read as an IEEE double, every key is
+// a non-negative non-NaN number (small keys are subnormal doubles, which this
+// file's kernels keep). For such doubles the numeric order is the unsigned
+// integer order of the bits, so the lists are kept as doubles and ordered
+// with v_min_f64 / v_max_f64 (one instruction each, no 64-bit integer
+// compare-and-select pairs).
+__device__ __forceinline__ double key_of(float dd, int idx) {
+    return __builtin_bit_cast(double, ((uint64_t)__float_as_uint(dd) << 32) | (uint32_t)idx);
+}
+__device__ __forceinline__ uint64_t bits_of(double k) { return __builtin_bit_cast(uint64_t, k); }
+__device__ __forceinline__ float key_dist(double k) {
+    return __uint_as_float((uint32_t)(bits_of(k) >> 32));
+}
+
+// Insert key into the ascending list b (the largest entry falls off).
+// Inserting the padding key leaves b unchanged, so callers insert
+// unconditionally instead of branching (a branch makes the compiler copy the
+// whole list).
 template <int K>
-__device__ __forceinline__ void topk_insert(uint64_t (&b)[K], uint64_t key) {
+__device__ __forceinline__ void topk_insert(double (&b)[K], double key) {
 #pragma unroll
     for (int i = 0; i < K; ++i) {
-        const uint64_t lo = b[i] < key ? b[i] : key;
-        key = b[i] < key ? key : b[i];
-        b[i] = lo;
+        const double hi = __builtin_fmax(b[i], key);
+        b[i] = __builtin_fmin(b[i], key);
+        key = hi;
     }
 }
 
@@ -340,23 +359,24 @@ constexpr int next_pow2(int k) {
 // bitonic sequence holding the M smallest of the padded union (so the K
 // smallest of a and b); a bitonic sorter then orders it.
 template <int K>
-__device__ __forceinline__ void merge_topk(uint64_t (&a)[K], const uint64_t (&b)[K]) {
+__device__ __forceinline__ void merge_topk(double (&a)[K], const double (&b)[K]) {
     constexpr int M = next_pow2(K);
-    uint64_t c[M];
+    const double pad = __builtin_bit_cast(double, PAD_KEY);
+    double c[M];
 #pragma unroll
     for (int i = 0; i < M; ++i) {
-        const uint64_t x = i < K ? a[i] : PAD_KEY;
-        const uint64_t y = (M - 1 - i) < K ? b[M - 1 - i] : PAD_KEY;
-        c[i] = x < y ? x : y;
+        const double x = i < K ? a[i] : pad;
+        const double y = (M - 1 - i) < K ? b[M - 1 - i] : pad;
+        c[i] = __builtin_fmin(x, y);
     }
 #pragma unroll
     for (int d = M / 2; d > 0; d >>= 1) {
 #pragma unroll
         for (int i = 0; i < M; ++i) {
             if ((i & d) == 0) {
-                const uint64_t x = c[i], y = c[i + d];
-                c[i] = x < y ? x : y;
-                c[i + d] = x < y ? y : x;
+                const double x = c[i], y = c[i + d];
+                c[i] = __builtin_fmin(x, y);
+                c[i + d] = __builtin_fmax(x, y);
             }
         }
     }
@@ -388,18 +408,19 @@ __global__ __launch_bounds__(256) void k_leaf_knn(
     __shared__ Node s_nodes[4][SB];
     __shared__ int s_offs[4][SB + 1];
     __shared__ uint8_t s_q[4][CQ][64];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int w = uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
     const int A = xcd_block(blockIdx.x, gridDim.x) * 4 + w;
     if (A >= n_leaves) return;
     const Node a = leaves[A];
-    const int lgS = a.count <= 16 ? 2 : (a.count <= 32 ? 1 : 0);  // log2 lanes per query
+    const int acount = uni(a.count);
+    const int lgS = acount <= 16 ? 2 : (acount <= 32 ? 1 : 0);  // log2 lanes per query
     const int S = 1 << lgS;
     const int q = lane & ((64 >> lgS) - 1), h = lane >> (6 - lgS);
-    const bool act = q < a.count;
+    const bool act = q < acount;
     const float4 me = pts[a.start + (act ? q : 0)];
     const int2 sg = seg[A];
-    const int2 *gl = list + sg.x;
-    const int len = sg.y;
+    const int2 *gl = list + uni(sg.x);
+    const int len = uni(sg.y);
     uint64_t *L = s_list[w];
     float4 *tile = s_tile[w];
     Node *nb = s_nodes[w];
@@ -407,37 +428,45 @@ __global__ __launch_bounds__(256) void k_leaf_knn(
     const bool staged = len <= LCAP;
     if (staged) stage_sorted(gl, len, L);
 
-    uint64_t best[K];
+    const double pad = __builtin_bit_cast(double, PAD_KEY);
+    double best[K];
 #pragma unroll
-    for (int i = 0; i < K; ++i) best[i] = PAD_KEY;
-    unsigned evals = 0, visited = 0;
+    for (int i = 0; i < K; ++i) best[i] = pad;
+    unsigned evals = 0, visited = 0, rounds = 0, steps = 0;
     int qn = 0;  // queued positions of this lane
 
+    // the group's k-th distance: an upper bound of the query's final k-th
+    auto group_kth = [&]() {
+        float v = key_dist(best[K - 1]);
+        if (lgS >= 1) v = fminf(v, __shfl_xor(v, 32, 64));
+        if (lgS >= 2) v = fminf(v, __shfl_xor(v, 16, 64));
+        return v;
+    };
     // insert the queued candidates of every lane into its top-k
     auto drain = [&]() {
         for (int c = 0; __ballot(c < qn); ++c) {
-            if (c < qn) {
-                const float4 s = tile[s_q[w][c][lane]];
-                const float dd = dist2_pts(me.x, me.y, me.z, s.x, s.y, s.z);
-                const uint64_t key =
-                    ((uint64_t)__float_as_uint(dd) << 32) | (uint32_t)__float_as_int(s.w);
-                if (key < best[K - 1]) topk_insert<K>(best, key);
-            }
+            ++rounds;
+            const bool has = c < qn;
+            const float4 s = tile[has ? s_q[w][c][lane] : 0];
+            const float dd = dist2_pts(me.x, me.y, me.z, s.x, s.y, s.z);
+            const double key = key_of(dd, __float_as_int(s.w));
+            topk_insert<K>(best, has ? key : pad);
         }
         qn = 0;
     };
 
     int t = 0;
     while (t < len) {
-        float kth = __uint_as_float((uint32_t)(best[K - 1] >> 32));
-        if (lgS >= 1) kth = fminf(kth, __shfl_xor(kth, 32, 64));
-        if (lgS >= 2) kth = fminf(kth, __shfl_xor(kth, 16, 64));
-        const float Rw = wave_max(act ? kth : -INFINITY);
-        // sources t .. t + nb_n - 1 of this batch (all with r_low <= Rw)
+        float kth = group_kth();
+        const float Rw = uni(wave_max(act ? kth : -INFINITY));
+        // sources t .. t + nb_n - 1 of this batch (all with r_low <= Rw); the
+        // first batch is one source, so that the top-k fills from the nearest
+        // leaf before anything else is filtered against it
+        const int sbl = t == 0 ? 1 : SB;
         int src = 0;
         float rl = INFINITY;
-        if (lane < SB && t + lane < len) list_entry(staged, L, gl, t + lane, src, rl);
-        const bool inb = lane < SB && t + lane < len && (!staged || rl <= Rw);
+        if (lane < sbl && t + lane < len) list_entry(staged, L, gl, t + lane, src, rl);
+        const bool inb = lane < sbl && t + lane < len && (!staged || rl <= Rw);
         const uint64_t inmask = __ballot(inb);  // a prefix of lanes 0..SB-1 (sorted)
         const int nb_n = __ffsll((unsigned long long)(~inmask)) - 1;
         if (nb_n == 0) break;
@@ -449,12 +478,13 @@ __global__ __launch_bounds__(256) void k_leaf_knn(
         unsigned any = needbits;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) any |= __shfl_xor(any, o, 64);
+        any = uni(any);
         // take needed sources in order while their points fit the tile
         // (every lane computes the same offsets; lane 0 keeps them in LDS)
         int take = 0, npts = 0;
         if (lane == 0) offs[0] = 0;
         for (int qq = 0; qq < nb_n; ++qq) {
-            const int c = (any >> qq) & 1u ? nb[qq].count : 0;
+            const int c = (any >> qq) & 1u ? uni(nb[qq].count) : 0;
             if (npts + c > TILE_PTS) break;
             npts += c;
             if (lane == 0) offs[qq + 1] = npts;
@@ -471,15 +501,25 @@ __global__ __launch_bounds__(256) void k_leaf_knn(
             if (!((any >> qq) & 1u)) continue;
             ++visited;
             const bool need = (needbits >> qq) & 1u;
-            const int f0 = offs[qq], f1 = offs[qq + 1];
+            const int f0 = uni(offs[qq]), f1 = uni(offs[qq + 1]);
             for (int j0 = f0; j0 < f1; j0 += CH * S) {
                 const int j1 = min(f1, j0 + CH * S);
-                for (int j = j0 + h; j < j1; j += S) {
-                    const float4 s = tile[j];
+                // uniform trip count: lane slice h takes position jj + h
+#pragma unroll 4
+                for (int jj = j0; jj < j1; jj += S) {
+                    const int j = jj + h;
+                    const float4 s = tile[min(j, j1 - 1)];
                     const float dd = dist2_pts(me.x, me.y, me.z, s.x, s.y, s.z);
-                    if (need && dd <= kth) s_q[w][qn++][lane] = (uint8_t)j;
+                    // written always, kept only if accepted (qn <= CQ - 1 here:
+                    // qn <= CQ - CH at the chunk start, at most CH steps)
+                    s_q[w][qn][lane] = (uint8_t)j;
+                    qn += (need && j < j1 && dd <= kth) ? 1 : 0;
                 }
-                if (__ballot(qn > CQ - CH)) drain();
+                steps += (unsigned)((j1 - j0 + S - 1) >> lgS);
+                if (__ballot(qn > CQ - CH)) {
+                    drain();
+                    kth = group_kth();
+                }
             }
             if (need) evals += (unsigned)((f1 - f0 - h + S - 1) >> lgS);
         }
@@ -489,13 +529,13 @@ __global__ __launch_bounds__(256) void k_leaf_knn(
     }
     // merge the partial lists of a query's lanes
     if (lgS >= 1) {
-        uint64_t other[K];
+        double other[K];
 #pragma unroll
         for (int i = 0; i < K; ++i) other[i] = __shfl_xor(best[i], 32, 64);
         merge_topk<K>(best, other);
     }
     if (lgS >= 2) {
-        uint64_t other[K];
+        double other[K];
 #pragma unroll
         for (int i = 0; i < K; ++i) other[i] = __shfl_xor(best[i], 16, 64);
         merge_topk<K>(best, other);
@@ -507,16 +547,18 @@ __global__ __launch_bounds__(256) void k_leaf_knn(
         float *od = out_d2 + row * K;
 #pragma unroll
         for (int r = 0; r < K; ++r) {
-            const uint64_t e = best[r];
-            const bool pad = e == PAD_KEY;
-            oi[r] = pad ? -1 : (int)(uint32_t)e - base;
-            od[r] = pad ? INFINITY : __uint_as_float((uint32_t)(e >> 32));
+            const uint64_t e = bits_of(best[r]);
+            const bool none = e == PAD_KEY;
+            oi[r] = none ? -1 : (int)(uint32_t)e - base;
+            od[r] = none ? INFINITY : __uint_as_float((uint32_t)(e >> 32));
         }
     }
     const int ev = wave_sum((int)evals);
     if (lane == 0) {
         atomicAdd(stats + 0, (unsigned long long)ev);
         atomicAdd(stats + 1, (unsigned long long)visited);
+        atomicAdd(stats + 2, (unsigned long long)rounds);
+        atomicAdd(stats + 3, (unsigned long long)steps);
     }
 }
 
@@ -550,6 +592,7 @@ jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s) 
     t->st.evaluations = 0;
     t->st.leaf_ms = t->st.total_ms = 0;
     t->st.reruns = 0;
+    t->st.insert_rounds = t->st.tile_steps = 0;
     if (t->n == 0) return JZ_OK;
 
     // counters: [0, P) list entries per level, [JZ_MAX_PLANES, +2) leaf stats
@@ -624,6 +667,8 @@ jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s) 
         t->st.leaf_pairs = t->st.list_entries[0];
         t->st.evaluations = (double)hc[JZ_MAX_PLANES];
         t->st.leaf_pairs_visited = (int64_t)hc[JZ_MAX_PLANES + 1];
+        t->st.insert_rounds = (int64_t)hc[JZ_MAX_PLANES + 2];
+        t->st.tile_steps = (int64_t)hc[JZ_MAX_PLANES + 3];
         if (ev.on) {
             float ms = 0;
             JZ_HIP(hipEventElapsedTime(&ms, ev[1], ev[2]));
