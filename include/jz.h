@@ -68,7 +68,7 @@ typedef struct jz_allocator {
 /* Build options (tree-plane hierarchy of the paper's section on the plane
  * based hierarchy; defaults follow its Eq. 8-9 and Alg. 1). */
 typedef struct jz_build_opts {
-    int leaf_max;          /* N_max^(0): most points per leaf. Default 48, range [1, 64]. */
+    int leaf_max;          /* N_max^(0): most points per leaf. Default 64, range [1, 64]. */
     int coarsen;           /* c in N_max^(p) = N_max^(0) c^p. Default 8, range [2, 64]. */
     int n_target;          /* stop adding planes when N / (N_max^(p)/2) < n_target. Default 1000. */
     int ngr;               /* top nodes per super node (NGR of Alg. 1). Default 32, range [1, 64]. */

@@ -273,7 +273,7 @@ extern "C" {
 
 void jz_default_opts(jz_build_opts *o) {
     if (!o) return;
-    o->leaf_max = 48;
+    o->leaf_max = 64;
     o->coarsen = 8;
     o->n_target = 1000;
     o->ngr = 32;

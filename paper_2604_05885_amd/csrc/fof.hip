@@ -47,7 +47,7 @@ __global__ __launch_bounds__(256) void k_fof_p2n(const int *__restrict__ par_spl
                                                  const int *__restrict__ whole_par,
                                                  int *__restrict__ whole, int *__restrict__ uf,
                                                  float b2, const float *__restrict__ b2n) {
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int w = uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
     const int P = xcd_block(blockIdx.x, gridDim.x) * 4 + w;
     if (P >= n_par) return;
     const int c0 = par_spl[P], c1 = par_spl[P + 1];
@@ -66,7 +66,7 @@ __global__ __launch_bounds__(256) void k_fof_p2n(const int *__restrict__ par_spl
 __global__ __launch_bounds__(256) void k_fof_l2p(const Node *__restrict__ leaves, int n_leaves,
                                                  const int *__restrict__ whole,
                                                  int *__restrict__ uf) {
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int w = uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
     const int A = xcd_block(blockIdx.x, gridDim.x) * 4 + w;
     if (A >= n_leaves || !whole[A]) return;
     const Node a = leaves[A];
@@ -103,13 +103,13 @@ __global__ __launch_bounds__(256) void k_fof_step(
     int2 *__restrict__ seg_out, int2 *__restrict__ list_out,
     unsigned long long *__restrict__ ctr, long long cap) {
     __shared__ Node s_tile[4][64];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int w = uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
     const int P = xcd_block(blockIdx.x, gridDim.x) * 4 + w;
     if (P >= n_par) return;
     const int2 sg = seg_in[P];
-    const int2 *gl = list_in + sg.x;
-    const int len = sg.y;
-    const int c0 = par_spl[P], c1 = par_spl[P + 1];
+    const int2 *gl = list_in + uni(sg.x);
+    const int len = uni(sg.y);
+    const int c0 = uni(par_spl[P]), c1 = uni(par_spl[P + 1]);
     Node *tile = s_tile[w];
     for (int cb = c0; cb < c1; cb += 64) {
         const int c = cb + lane;
@@ -134,10 +134,10 @@ __global__ __launch_bounds__(256) void k_fof_step(
             }
         }
         const int incl = wave_incl_scan(cnt);
-        const int total = __shfl(incl, 63, 64);
+        const int total = uni(__shfl(incl, 63, 64));
         unsigned long long base = 0;
         if (lane == 0) base = atomicAdd(ctr, (unsigned long long)total);
-        base = __shfl(base, 0, 64);
+        base = uni((unsigned long long)__shfl(base, 0, 64));
         const long long pos = (long long)base + (incl - cnt);
         const bool ok = (long long)base + total <= cap;
         if (!ok) {
@@ -200,18 +200,19 @@ __global__ __launch_bounds__(256) void k_leaf_fof(
     __shared__ Node s_nodes[4][FSB];
     __shared__ int s_offs[4][FSB + 1];
     __shared__ int s_root[4][64];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int w = uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
     const int A = xcd_block(blockIdx.x, gridDim.x) * 4 + w;
     if (A >= n_leaves) return;
     const Node a = leaves[A];
-    const bool act = lane < a.count;
-    const int my = a.start + (act ? lane : 0);
+    const int astart = uni(a.start);
+    const bool act = lane < uni(a.count);
+    const int my = astart + (act ? lane : 0);
     const float4 me = pts[my];
     const float bb = b2n ? b2n[A] : b2;
-    const int wA = whole[A];
+    const int wA = uni(whole[A]);
     const int2 sg = seg[A];
-    const int2 *gl = list + sg.x;
-    const int len = sg.y;
+    const int2 *gl = list + uni(sg.x);
+    const int len = uni(sg.y);
     float4 *tile = s_tile[w];
     Node *nb = s_nodes[w];
     int *offs = s_offs[w];
@@ -220,7 +221,7 @@ __global__ __launch_bounds__(256) void k_leaf_fof(
     unsigned evals = 0;
     for (int t = 0; t < len;) {
         const int nb_n = min(FSB, len - t);
-        const int rA = wA ? uf_find(uf, a.start) : -1;
+        const int rA = wA ? uni(uf_find(uf, astart)) : -1;
         bool skip = false;
         int wB = 0;
         if (lane < nb_n) {
@@ -240,10 +241,11 @@ __global__ __launch_bounds__(256) void k_leaf_fof(
         unsigned any = needbits;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) any |= __shfl_xor(any, o, 64);
+        any = uni(any);
         int take = 0, npts = 0;
         if (lane == 0) offs[0] = 0;
         for (int q = 0; q < nb_n; ++q) {
-            const int c = (any >> q) & 1u ? nb[q].count : 0;
+            const int c = (any >> q) & 1u ? uni(nb[q].count) : 0;
             if (npts + c > FTILE) break;
             npts += c;
             if (lane == 0) offs[q + 1] = npts;
@@ -260,8 +262,8 @@ __global__ __launch_bounds__(256) void k_leaf_fof(
             if (!((any >> q) & 1u)) continue;
             const bool need = (needbits >> q) & 1u;
             const bool wB = (wholemask >> q) & 1u;
-            const int f0 = offs[q], f1 = offs[q + 1];
-            const int b0 = nb[q].start;
+            const int f0 = uni(offs[q]), f1 = uni(offs[q + 1]);
+            const int b0 = uni(nb[q].start);
             // 1: which points of this source link to this lane's point
             uint64_t lm = 0;
             if (need) {

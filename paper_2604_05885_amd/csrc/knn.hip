@@ -18,6 +18,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <type_traits>
 #include <vector>
 
 #include "jz_device.h"
@@ -126,7 +127,7 @@ __device__ __forceinline__ void for_source_batches(bool staged, const uint64_t *
     const int lane = lane_id();
     int t = 0, skip = 0;
     while (t < len) {
-        const float Rw = rw();
+        const float Rw = uni(rw());
         int src = 0, s0 = 0, cnt = 0;
         float rl = 0.0f;
         const bool valid = t + lane < len;
@@ -149,7 +150,7 @@ __device__ __forceinline__ void for_source_batches(bool staged, const uint64_t *
         int nF;
         if (ntake == 0) {
             // the first source alone overflows the buffer: take FCAP of its children
-            const int b0 = __shfl(s0, 0, 64);
+            const int b0 = uni(__shfl(s0, 0, 64));
             for (int f = lane; f < FCAP; f += 64) {
                 F[f] = nodes[b0 + f];
                 FI[f] = b0 + f;
@@ -164,7 +165,7 @@ __device__ __forceinline__ void for_source_batches(bool staged, const uint64_t *
                     FI[off + q] = s0 + q;
                 }
             }
-            nF = __shfl(incl, ntake - 1, 64);
+            nF = uni(__shfl(incl, ntake - 1, 64));
             t += ntake;
             skip = 0;
         }
@@ -192,13 +193,13 @@ __global__ __launch_bounds__(256) void k_knn_step(
     __shared__ uint64_t s_list[4][LCAP];
     __shared__ Node s_f[4][FCAP];
     __shared__ int s_fi[4][FCAP];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int w = uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
     const int P = xcd_block(blockIdx.x, gridDim.x) * 4 + w;
     if (P >= n_par) return;
     const int2 sg = seg_in[P];
-    const int2 *gl = list_in + sg.x;
-    const int len = sg.y;
-    const int c0 = par_spl[P], c1 = par_spl[P + 1];
+    const int2 *gl = list_in + uni(sg.x);
+    const int len = uni(sg.y);
+    const int c0 = uni(par_spl[P]), c1 = uni(par_spl[P + 1]);
     uint64_t *L = s_list[w];
     Node *F = s_f[w];
     int *FI = s_fi[w];
@@ -264,7 +265,7 @@ __global__ __launch_bounds__(256) void k_knn_step(
             R = best;
             wave_lds_sync();
         }
-        const float Rw = wave_max(act ? R : -INFINITY);
+        const float Rw = uni(wave_max(act ? R : -INFINITY));
         // pass 2: count
         int cnt = 0;
         for_source_batches(
@@ -274,10 +275,10 @@ __global__ __launch_bounds__(256) void k_knn_step(
             });
         // reserve: lanes are child-major, so a wave scan gives contiguous segments
         const int incl = wave_incl_scan(cnt);
-        const int total = __shfl(incl, 63, 64);
+        const int total = uni(__shfl(incl, 63, 64));
         unsigned long long base = 0;
         if (lane == 0) base = atomicAdd(ctr, (unsigned long long)total);
-        base = __shfl(base, 0, 64);
+        base = uni((unsigned long long)__shfl(base, 0, 64));
         const bool ok = (long long)base + total <= cap;
         const int gfirst = (ci << lg), glast = gfirst + G - 1;
         const int gstart = __shfl(incl - cnt, gfirst & 63, 64);
@@ -317,17 +318,42 @@ __device__ __forceinline__ float key_dist(double k) {
     return __uint_as_float((uint32_t)(bits_of(k) >> 32));
 }
 
+constexpr int next_pow2(int k) {
+    int m = 1;
+    while (m < k) m <<= 1;
+    return m;
+}
+
+// An ascending list of K keys held in one or two vector registers tuples of
+// at most 16 doubles. As a vector the list is one register tuple that the
+// compiler updates in place; as an array of doubles every insertion renames
+// the entries and loops pay a copy of the whole list per iteration.
+template <int K>
+struct TopK {
+    static constexpr int W = K <= 16 ? next_pow2(K) : 16;
+    static constexpr int NV = (K + W - 1) / W;
+    typedef double vec __attribute__((ext_vector_type(W)));
+    vec v[NV];
+    __device__ __forceinline__ double get(int i) const { return v[i / W][i % W]; }
+    __device__ __forceinline__ void set(int i, double x) { v[i / W][i % W] = x; }
+};
+
 // Insert key into the ascending list b (the largest entry falls off).
 // Inserting the padding key leaves b unchanged, so callers insert
-// unconditionally instead of branching (a branch makes the compiler copy the
-// whole list).
+// unconditionally instead of branching. Each slot computes the carried
+// maximum first and then the slot's minimum in place; the scheduling fence
+// keeps that order, which lets the register allocator update the list in
+// place (with the maxima hoisted, it rotates the list through other
+// registers and pays a copy of every entry per insertion).
 template <int K>
-__device__ __forceinline__ void topk_insert(double (&b)[K], double key) {
+__device__ __forceinline__ void topk_insert(TopK<K> &b, double key) {
 #pragma unroll
     for (int i = 0; i < K; ++i) {
-        const double hi = __builtin_fmax(b[i], key);
-        b[i] = __builtin_fmin(b[i], key);
+        const double e = b.get(i);
+        const double hi = __builtin_fmax(key, e);
+        b.set(i, __builtin_fmin(e, key));
         key = hi;
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -344,29 +370,23 @@ __device__ __forceinline__ float point_box_low2(const float4 &q, const Node &b) 
 }
 
 constexpr int SB = 8;         // source leaves examined per batch
-constexpr int TILE_PTS = 128; // source points staged per batch (positions fit a byte)
+constexpr int TILE_PTS = 256; // source points staged per batch (positions fit a byte)
 constexpr int CQ = 32;        // queued candidate positions per lane
 constexpr int CH = 8;         // tile positions a lane scans between queue checks
-
-constexpr int next_pow2(int k) {
-    int m = 1;
-    while (m < k) m <<= 1;
-    return m;
-}
 
 // Keep the K smallest of two ascending key lists a and b in a (ascending).
 // With both lists padded to M = next power of two, min(a[i], b[M-1-i]) is a
 // bitonic sequence holding the M smallest of the padded union (so the K
 // smallest of a and b); a bitonic sorter then orders it.
 template <int K>
-__device__ __forceinline__ void merge_topk(double (&a)[K], const double (&b)[K]) {
+__device__ __forceinline__ void merge_topk(TopK<K> &a, const TopK<K> &b) {
     constexpr int M = next_pow2(K);
     const double pad = __builtin_bit_cast(double, PAD_KEY);
     double c[M];
 #pragma unroll
     for (int i = 0; i < M; ++i) {
-        const double x = i < K ? a[i] : pad;
-        const double y = (M - 1 - i) < K ? b[M - 1 - i] : pad;
+        const double x = i < K ? a.get(i) : pad;
+        const double y = (M - 1 - i) < K ? b.get(M - 1 - i) : pad;
         c[i] = __builtin_fmin(x, y);
     }
 #pragma unroll
@@ -381,7 +401,7 @@ __device__ __forceinline__ void merge_topk(double (&a)[K], const double (&b)[K])
         }
     }
 #pragma unroll
-    for (int i = 0; i < K; ++i) a[i] = c[i];
+    for (int i = 0; i < K; ++i) a.set(i, c[i]);
 }
 
 // Leaf stage, one wave per receiving leaf. A leaf of at most 16 (32) points
@@ -429,48 +449,76 @@ __global__ __launch_bounds__(256) void k_leaf_knn(
     if (staged) stage_sorted(gl, len, L);
 
     const double pad = __builtin_bit_cast(double, PAD_KEY);
-    double best[K];
+    TopK<K> best;
 #pragma unroll
-    for (int i = 0; i < K; ++i) best[i] = pad;
+    for (int i = 0; i < K; ++i) best.set(i, pad);
     unsigned evals = 0, visited = 0, rounds = 0, steps = 0;
-    int qn = 0;  // queued positions of this lane
+    // candidate queue of this lane: positions at q0, q0 + 64, ... up to qp
+    uint8_t *const q0 = &s_q[w][0][lane];
+    uint8_t *qp = q0;
+    const uint8_t *const qlim = q0 + 64 * (CQ - CH);
 
     // the group's k-th distance: an upper bound of the query's final k-th
     auto group_kth = [&]() {
-        float v = key_dist(best[K - 1]);
+        float v = key_dist(best.get(K - 1));
         if (lgS >= 1) v = fminf(v, __shfl_xor(v, 32, 64));
         if (lgS >= 2) v = fminf(v, __shfl_xor(v, 16, 64));
         return v;
     };
     // insert the queued candidates of every lane into its top-k
     auto drain = [&]() {
-        for (int c = 0; __ballot(c < qn); ++c) {
+        const int qn = (int)(qp - q0) >> 6;
+        // a scalar trip count (a loop on a ballot compiles to a divergent
+        // loop, whose exit handling copies the list every round)
+        const int nr = uni(wave_max_int(qn));
+        for (int c = 0; c < nr; ++c) {
             ++rounds;
             const bool has = c < qn;
-            const float4 s = tile[has ? s_q[w][c][lane] : 0];
+            // the slot is read unconditionally (a branch around the read
+            // would make the compiler copy the list every round)
+            const int qv = q0[64 * c];
+            const float4 s = tile[has ? qv : 0];
             const float dd = dist2_pts(me.x, me.y, me.z, s.x, s.y, s.z);
             const double key = key_of(dd, __float_as_int(s.w));
             topk_insert<K>(best, has ? key : pad);
         }
-        qn = 0;
+        qp = q0;
     };
 
+    // The list entries of the next batch window and their Node records are
+    // fetched one batch ahead (into registers of lanes 0..SB-1), so the Node
+    // loads overlap the current batch's work.
+    int pf_src = 0;
+    float pf_rl = INFINITY;
+    bool pf_ok = false;
+    float4 pf_lo = make_float4(0, 0, 0, 0), pf_hi = pf_lo;  // the Node record's two halves
+    auto fetch = [&](int t0, int cnt) {
+        pf_ok = lane < cnt && t0 + lane < len;
+        if (pf_ok) {
+            list_entry(staged, L, gl, t0 + lane, pf_src, pf_rl);
+            const float4 *rec = reinterpret_cast<const float4 *>(leaves + pf_src);
+            pf_lo = rec[0];
+            pf_hi = rec[1];
+        }
+    };
+    // the first batch is one source, so that the top-k fills from the
+    // nearest leaf before anything else is filtered against it
+    fetch(0, 1);
     int t = 0;
     while (t < len) {
         float kth = group_kth();
         const float Rw = uni(wave_max(act ? kth : -INFINITY));
-        // sources t .. t + nb_n - 1 of this batch (all with r_low <= Rw); the
-        // first batch is one source, so that the top-k fills from the nearest
-        // leaf before anything else is filtered against it
-        const int sbl = t == 0 ? 1 : SB;
-        int src = 0;
-        float rl = INFINITY;
-        if (lane < sbl && t + lane < len) list_entry(staged, L, gl, t + lane, src, rl);
-        const bool inb = lane < sbl && t + lane < len && (!staged || rl <= Rw);
-        const uint64_t inmask = __ballot(inb);  // a prefix of lanes 0..SB-1 (sorted)
+        // sources t .. t + nb_n - 1 of this batch: the window's entries with
+        // r_low <= Rw (a prefix, the list being sorted by r_low)
+        const bool inb = pf_ok && (!staged || pf_rl <= Rw);
+        const uint64_t inmask = __ballot(inb);
         const int nb_n = __ffsll((unsigned long long)(~inmask)) - 1;
         if (nb_n == 0) break;
-        if (lane < nb_n) nb[lane] = leaves[src];
+        if (lane < nb_n) {
+            float4 *rec = reinterpret_cast<float4 *>(nb + lane);
+            rec[0] = pf_lo;
+            rec[1] = pf_hi;
+        }
         wave_lds_sync();
         unsigned needbits = 0;
         for (int qq = 0; qq < nb_n; ++qq)
@@ -479,65 +527,92 @@ __global__ __launch_bounds__(256) void k_leaf_knn(
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) any |= __shfl_xor(any, o, 64);
         any = uni(any);
-        // take needed sources in order while their points fit the tile
-        // (every lane computes the same offsets; lane 0 keeps them in LDS)
+        // take needed sources in order while their points fit the tile; each
+        // occupies a multiple of S positions (every lane computes the same
+        // offsets; lane 0 keeps them in LDS for the scan)
         int take = 0, npts = 0;
+        int o_r[SB + 1];
+        o_r[0] = 0;
         if (lane == 0) offs[0] = 0;
-        for (int qq = 0; qq < nb_n; ++qq) {
-            const int c = (any >> qq) & 1u ? uni(nb[qq].count) : 0;
-            if (npts + c > TILE_PTS) break;
-            npts += c;
+#pragma unroll
+        for (int qq = 0; qq < SB; ++qq) {
+            const bool want = qq < nb_n && take == qq;
+            const int c = want && ((any >> qq) & 1u) ? (uni(nb[qq].count) + S - 1) & -S : 0;
+            if (want && npts + c <= TILE_PTS) {
+                npts += c;
+                take = qq + 1;
+            }
+            o_r[qq + 1] = npts;
             if (lane == 0) offs[qq + 1] = npts;
-            take = qq + 1;
         }
-        wave_lds_sync();
-        for (int f = lane; f < npts; f += 64) {
-            int qq = 0;
-            while (offs[qq + 1] <= f) ++qq;
-            tile[f] = pts[nb[qq].start + (f - offs[qq])];
+        // stage the taken sources' points (one loop per source; the loads are
+        // independent). Filler positions hold a point at +inf with index -1:
+        // its key is the padding key, so accepting it changes nothing.
+#pragma unroll
+        for (int qq = 0; qq < SB; ++qq) {
+            if (qq < take && o_r[qq + 1] > o_r[qq]) {
+                const int cnt = uni(nb[qq].count), st = uni(nb[qq].start);
+                for (int f = lane; f < o_r[qq + 1] - o_r[qq]; f += 64)
+                    tile[o_r[qq] + f] = f < cnt ? pts[st + f]
+                                                : make_float4(INFINITY, INFINITY, INFINITY,
+                                                              __int_as_float(-1));
+            }
         }
+        // next window
+        fetch(t + take, SB);
         wave_lds_sync();
-        for (int qq = 0; qq < take; ++qq) {
-            if (!((any >> qq) & 1u)) continue;
-            ++visited;
-            const bool need = (needbits >> qq) & 1u;
-            const int f0 = uni(offs[qq]), f1 = uni(offs[qq + 1]);
-            for (int j0 = f0; j0 < f1; j0 += CH * S) {
-                const int j1 = min(f1, j0 + CH * S);
-                // uniform trip count: lane slice h takes position jj + h
+        // the S lanes of a query take positions jj + h of every S-aligned step
+        auto scan = [&](auto s_const) {
+            constexpr int SS = decltype(s_const)::value;
+            for (int qq = 0; qq < take; ++qq) {
+                if (!((any >> qq) & 1u)) continue;
+                ++visited;
+                const bool need = (needbits >> qq) & 1u;
+                const int f0 = uni(offs[qq]), f1 = uni(offs[qq + 1]);
+                for (int j0 = f0; j0 < f1; j0 += CH * SS) {
+                    const int j1 = min(f1, j0 + CH * SS);
+                    // a lane whose query cannot reach this source accepts nothing
+                    const float thr = need ? kth : -1.0f;
 #pragma unroll 4
-                for (int jj = j0; jj < j1; jj += S) {
-                    const int j = jj + h;
-                    const float4 s = tile[min(j, j1 - 1)];
-                    const float dd = dist2_pts(me.x, me.y, me.z, s.x, s.y, s.z);
-                    // written always, kept only if accepted (qn <= CQ - 1 here:
-                    // qn <= CQ - CH at the chunk start, at most CH steps)
-                    s_q[w][qn][lane] = (uint8_t)j;
-                    qn += (need && j < j1 && dd <= kth) ? 1 : 0;
+                    for (int jj = j0; jj < j1; jj += SS) {
+                        const int j = jj + h;
+                        const float4 p = tile[j];
+                        const float dd = dist2_pts(me.x, me.y, me.z, p.x, p.y, p.z);
+                        // written always, kept only if accepted (at most CH
+                        // steps from qn <= CQ - CH, so the slot exists)
+                        *qp = (uint8_t)j;
+                        qp += dd <= thr ? 64 : 0;
+                    }
+                    steps += (unsigned)((j1 - j0) / SS);
+                    if (__ballot(qp > qlim)) {
+                        drain();
+                        kth = group_kth();
+                    }
                 }
-                steps += (unsigned)((j1 - j0 + S - 1) >> lgS);
-                if (__ballot(qn > CQ - CH)) {
-                    drain();
-                    kth = group_kth();
+                if (need) {
+                    const int cnt = uni(nb[qq].count);
+                    evals += cnt > h ? (unsigned)((cnt - h + SS - 1) / SS) : 0u;
                 }
             }
-            if (need) evals += (unsigned)((f1 - f0 - h + S - 1) >> lgS);
-        }
+        };
+        if (lgS == 2) scan(std::integral_constant<int, 4>());
+        else if (lgS == 1) scan(std::integral_constant<int, 2>());
+        else scan(std::integral_constant<int, 1>());
         drain();
         wave_lds_sync();
         t += take;
     }
     // merge the partial lists of a query's lanes
     if (lgS >= 1) {
-        double other[K];
+        TopK<K> other;
 #pragma unroll
-        for (int i = 0; i < K; ++i) other[i] = __shfl_xor(best[i], 32, 64);
+        for (int i = 0; i < K; ++i) other.set(i, __shfl_xor(best.get(i), 32, 64));
         merge_topk<K>(best, other);
     }
     if (lgS >= 2) {
-        double other[K];
+        TopK<K> other;
 #pragma unroll
-        for (int i = 0; i < K; ++i) other[i] = __shfl_xor(best[i], 16, 64);
+        for (int i = 0; i < K; ++i) other.set(i, __shfl_xor(best.get(i), 16, 64));
         merge_topk<K>(best, other);
     }
     if (act && h == 0) {
@@ -547,7 +622,7 @@ __global__ __launch_bounds__(256) void k_leaf_knn(
         float *od = out_d2 + row * K;
 #pragma unroll
         for (int r = 0; r < K; ++r) {
-            const uint64_t e = bits_of(best[r]);
+            const uint64_t e = bits_of(best.get(r));
             const bool none = e == PAD_KEY;
             oi[r] = none ? -1 : (int)(uint32_t)e - base;
             od[r] = none ? INFINITY : __uint_as_float((uint32_t)(e >> 32));

@@ -174,7 +174,7 @@ def test_tree_against_plane_reference(jz):
         assert np.array_equal(ex["order"], order)
         assert np.array_equal(ex["keys"], want_keys[order])
         lv = planes.key_gap_levels(want_keys[order])
-        nmax = [48 * 8 ** q for q in range(st["planes"])]
+        nmax = [opts.leaf_max * opts.coarsen ** q for q in range(st["planes"])]
         ref = planes.planes(list(lv), nmax)
         for q in range(st["planes"]):
             got = t.export(plane=q)["spl"]
