@@ -172,15 +172,24 @@ __device__ __forceinline__ void uf_union(int *par, int a, int b) {
 
 // ---------------------------------------------------------------------------
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
-// L2). Remap so that each XCD works on one contiguous range of work items,
-// which keeps neighbouring z-order nodes (which share source data) in the
-// same L2.
+// L2). Remap so that each XCD works on runs of XCD_RUN consecutive
+// workgroups, the runs dealt to the XCDs in turn: neighbouring z-order nodes
+// (which share source data) stay in the same L2, while the cost of dense and
+// sparse regions spreads evenly over the XCDs (one contiguous range per XCD
+// leaves the XCD with the densest range finishing last). Workgroups past the
+// last complete round of runs take one contiguous range per XCD.
+constexpr int XCD_RUN = 4;
 __device__ __forceinline__ int xcd_block(int bid, int nblocks) {
+    constexpr int per = 8 * XCD_RUN;
+    const int full = nblocks / per;
     const int x = bid & 7;
-    const int i = bid >> 3;
-    const int q = nblocks >> 3;
-    const int r = nblocks & 7;
-    return x * q + (x < r ? x : r) + i;
+    if (bid < full * per) {
+        const int i = bid >> 3;
+        return ((i / XCD_RUN) * 8 + x) * XCD_RUN + (i % XCD_RUN);
+    }
+    const int b = (bid - full * per) >> 3, n = nblocks - full * per;
+    const int q = n >> 3, r = n & 7;
+    return full * per + x * q + (x < r ? x : r) + b;
 }
 
 __device__ __forceinline__ unsigned bitlen64(uint64_t v) { return v ? 64u - __clzll(v) : 0u; }

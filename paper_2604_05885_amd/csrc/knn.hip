@@ -404,6 +404,71 @@ __device__ __forceinline__ void merge_topk(TopK<K> &a, const TopK<K> &b) {
     for (int i = 0; i < K; ++i) a.set(i, c[i]);
 }
 
+// Sort C keys ascending in registers (bitonic sorting network, C a power of 2).
+template <int C>
+__device__ __forceinline__ void sort_keys(double (&a)[C]) {
+#pragma unroll
+    for (int k = 2; k <= C; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+            for (int i = 0; i < C; ++i) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const double x = a[i], y = a[l];
+                    const double lo = __builtin_fmin(x, y), hi = __builtin_fmax(x, y);
+                    a[i] = (i & k) == 0 ? lo : hi;
+                    a[l] = (i & k) == 0 ? hi : lo;
+                }
+            }
+        }
+    }
+}
+
+// Merge an ascending chunk of C keys into the top-k list (as merge_topk, the
+// chunk padded to M with padding keys).
+template <int K, int C>
+__device__ __forceinline__ void merge_chunk(TopK<K> &a, const double (&ch)[C]) {
+    constexpr int M = next_pow2(K);
+    if constexpr (M == K) {
+        // in place: only the last C entries meet a chunk key
+#pragma unroll
+        for (int i = M - C; i < M; ++i) a.set(i, __builtin_fmin(a.get(i), ch[M - 1 - i]));
+#pragma unroll
+        for (int d = M / 2; d > 0; d >>= 1) {
+#pragma unroll
+            for (int i = 0; i < M; ++i) {
+                if ((i & d) == 0) {
+                    const double x = a.get(i), y = a.get(i + d);
+                    a.set(i, __builtin_fmin(x, y));
+                    a.set(i + d, __builtin_fmax(x, y));
+                }
+            }
+        }
+        return;
+    }
+    const double pad = __builtin_bit_cast(double, PAD_KEY);
+    double c[M];
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+        const double x = i < K ? a.get(i) : pad;
+        c[i] = (M - 1 - i) < C ? __builtin_fmin(x, ch[M - 1 - i]) : x;
+    }
+#pragma unroll
+    for (int d = M / 2; d > 0; d >>= 1) {
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+            if ((i & d) == 0) {
+                const double x = c[i], y = c[i + d];
+                c[i] = __builtin_fmin(x, y);
+                c[i + d] = __builtin_fmax(x, y);
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < K; ++i) a.set(i, c[i]);
+}
+
 // Leaf stage, one wave per receiving leaf. A leaf of at most 16 (32) points
 // gives each query 4 (2) lanes; the lanes of a query scan interleaved slices
 // of every staged tile, keep their own top-k, and prune with the smallest
@@ -564,6 +629,35 @@ __global__ __launch_bounds__(256) void k_leaf_knn(
         // the S lanes of a query take positions jj + h of every S-aligned step
         auto scan = [&](auto s_const) {
             constexpr int SS = decltype(s_const)::value;
+            if (t == 0) {
+                // the first source (one with r_low = 0) meets an empty top-k:
+                // every point is accepted, so its points are merged in sorted
+                // chunks instead of being queued and inserted one by one
+                constexpr int C = K < 8 ? next_pow2(K) : (K <= 16 ? 8 : 16);
+                if (take == 1 && (any & 1u)) {
+                    ++visited;
+                    const int f0 = uni(offs[0]), f1 = uni(offs[1]);
+                    for (int j0 = f0; j0 < f1; j0 += C * SS) {
+                        double ch[C];
+#pragma unroll
+                        for (int u = 0; u < C; ++u) {
+                            if (j0 + u * SS < f1) {
+                                const float4 p = tile[j0 + u * SS + h];
+                                const float dd = dist2_pts(me.x, me.y, me.z, p.x, p.y, p.z);
+                                ch[u] = key_of(dd, __float_as_int(p.w));
+                            } else {
+                                ch[u] = pad;
+                            }
+                        }
+                        sort_keys<C>(ch);
+                        merge_chunk<K, C>(best, ch);
+                        steps += (unsigned)((min(f1, j0 + C * SS) - j0) / SS);
+                    }
+                    const int cnt = uni(nb[0].count);
+                    if (act) evals += cnt > h ? (unsigned)((cnt - h + SS - 1) / SS) : 0u;
+                }
+                return;
+            }
             for (int qq = 0; qq < take; ++qq) {
                 if (!((any >> qq) & 1u)) continue;
                 ++visited;
