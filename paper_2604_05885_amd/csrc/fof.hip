@@ -42,13 +42,13 @@ __global__ void k_node_b2(const int *__restrict__ node_set, int64_t L,
 }
 
 // ParentToNode: one wave per parent, lanes over its children.
-__global__ __launch_bounds__(256) void k_fof_p2n(const int *__restrict__ par_spl,
+__global__ __launch_bounds__(64 * WPB) void k_fof_p2n(const int *__restrict__ par_spl,
                                                  const Node *__restrict__ nodes, int n_par,
                                                  const int *__restrict__ whole_par,
                                                  int *__restrict__ whole, int *__restrict__ uf,
                                                  float b2, const float *__restrict__ b2n) {
-    const int w = uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
-    const int P = xcd_block(blockIdx.x, gridDim.x) * 4 + w;
+    const int w = WPB == 1 ? 0 : uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+    const int P = xcd_block(blockIdx.x, gridDim.x) * WPB + w;
     if (P >= n_par) return;
     const int c0 = par_spl[P], c1 = par_spl[P + 1];
     const int wp = whole_par ? whole_par[P] : 0;
@@ -63,11 +63,11 @@ __global__ __launch_bounds__(256) void k_fof_p2n(const int *__restrict__ par_spl
 }
 
 // whole leaves: every point points at the leaf's first point
-__global__ __launch_bounds__(256) void k_fof_l2p(const Node *__restrict__ leaves, int n_leaves,
+__global__ __launch_bounds__(64 * WPB) void k_fof_l2p(const Node *__restrict__ leaves, int n_leaves,
                                                  const int *__restrict__ whole,
                                                  int *__restrict__ uf) {
-    const int w = uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
-    const int A = xcd_block(blockIdx.x, gridDim.x) * 4 + w;
+    const int w = WPB == 1 ? 0 : uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+    const int A = xcd_block(blockIdx.x, gridDim.x) * WPB + w;
     if (A >= n_leaves || !whole[A]) return;
     const Node a = leaves[A];
     for (int i = a.start + 1 + lane; i < a.start + a.count; i += 64) uf[i] = a.start;
@@ -96,15 +96,15 @@ __device__ __forceinline__ int fof_case(const Node &me, int c, const Node &o, in
 // Pass A links and counts the pairs to descend into; pass B re-evaluates and
 // writes them (the group state only merges between the passes, so pass B
 // emits a subset of what pass A counted; the segment length is what it wrote).
-__global__ __launch_bounds__(256) void k_fof_step(
+__global__ __launch_bounds__(64 * WPB) void k_fof_step(
     const int2 *__restrict__ seg_in, const int2 *__restrict__ list_in,
     const int *__restrict__ par_spl, const Node *__restrict__ nodes, int n_par, float b2,
     const float *__restrict__ b2n, int *__restrict__ whole, int *__restrict__ uf,
     int2 *__restrict__ seg_out, int2 *__restrict__ list_out,
-    unsigned long long *__restrict__ ctr, long long cap) {
-    __shared__ Node s_tile[4][64];
-    const int w = uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
-    const int P = xcd_block(blockIdx.x, gridDim.x) * 4 + w;
+    unsigned long long *__restrict__ ctr, long long cap, unsigned long long *overflow) {
+    __shared__ Node s_tile[WPB][64];
+    const int w = WPB == 1 ? 0 : uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+    const int P = xcd_block(blockIdx.x, gridDim.x) * WPB + w;
     if (P >= n_par) return;
     const int2 sg = seg_in[P];
     const int2 *gl = list_in + uni(sg.x);
@@ -135,12 +135,17 @@ __global__ __launch_bounds__(256) void k_fof_step(
         }
         const int incl = wave_incl_scan(cnt);
         const int total = uni(__shfl(incl, 63, 64));
-        unsigned long long base = 0;
-        if (lane == 0) base = atomicAdd(ctr, (unsigned long long)total);
-        base = uni((unsigned long long)__shfl(base, 0, 64));
+        // segment in arena P % LIST_ARENAS (cap entries each)
+        const int ar = P & (LIST_ARENAS - 1);
+        unsigned long long lb = 0;
+        if (lane == 0) lb = atomicAdd(ctr + ar, (unsigned long long)total);
+        lb = uni((unsigned long long)__shfl(lb, 0, 64));
+        const unsigned long long base = (unsigned long long)ar * (unsigned long long)cap + lb;
         const long long pos = (long long)base + (incl - cnt);
-        const bool ok = (long long)base + total <= cap;
+        const bool ok = (long long)lb + total <= cap;
         if (!ok) {
+            // lists below are incomplete: the leaf stage of this attempt exits
+            if (lane == 0) *overflow = 1;
             if (act) seg_out[c] = make_int2(0, 0);
             continue;
         }
@@ -192,17 +197,19 @@ __device__ __forceinline__ float point_box_low2_f(const float4 &q, const Node &b
 // parallel, and unions made where the roots differ (a lane's own root is
 // cached; groups only ever merge, so equal roots, even looked up at different
 // times, mean already connected). Two whole leaves need only one link.
-__global__ __launch_bounds__(256) void k_leaf_fof(
+__global__ __launch_bounds__(64 * WPB) void k_leaf_fof(
     const int2 *__restrict__ seg, const int2 *__restrict__ list, const Node *__restrict__ leaves,
     const float4 *__restrict__ pts, int n_leaves, float b2, const float *__restrict__ b2n,
-    const int *__restrict__ whole, int *__restrict__ uf, unsigned long long *__restrict__ stats) {
-    __shared__ float4 s_tile[4][FTILE];
-    __shared__ Node s_nodes[4][FSB];
-    __shared__ int s_offs[4][FSB + 1];
-    __shared__ int s_root[4][64];
-    const int w = uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
-    const int A = xcd_block(blockIdx.x, gridDim.x) * 4 + w;
-    if (A >= n_leaves) return;
+    const int *__restrict__ whole, int *__restrict__ uf, unsigned long long *__restrict__ stats,
+    const unsigned long long *__restrict__ overflow) {
+    __shared__ float4 s_tile[WPB][FTILE];
+    __shared__ Node s_nodes[WPB][FSB];
+    __shared__ int s_offs[WPB][FSB + 1];
+    __shared__ int s_root[WPB][64];
+    const int w = WPB == 1 ? 0 : uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+    const int A = xcd_block(blockIdx.x, gridDim.x) * WPB + w;
+    // a level of this attempt overflowed (it is rerun): nothing to do
+    if (A >= n_leaves || *overflow) return;
     const Node a = leaves[A];
     const int astart = uni(a.start);
     const bool act = lane < uni(a.count);
@@ -309,7 +316,7 @@ __global__ __launch_bounds__(256) void k_leaf_fof(
         t += take;
     }
     const int ev = wave_sum((int)evals);
-    if (lane == 0) atomicAdd(stats, (unsigned long long)ev);
+    if (lane == 0) atomicAdd(stats + (A & (STAT_SLOTS - 1)), (unsigned long long)ev);
 }
 
 // Root of every point (a read-only find: no other thread writes uf[i] now)
@@ -382,7 +389,9 @@ jz_status run_fof(jz_tree *t, const float *b2_set_host, int32_t *label, hipStrea
     const bool sets = t->nsets > 1;
     const float b2 = b2_set_host[0];
     DBuf d_ctr, d_uf, d_min, d_b2set;
-    JZ_TRY(d_ctr.get(ac, (JZ_MAX_PLANES + 4) * sizeof(unsigned long long), s));
+    // counters: one leaf statistic (evaluations)
+    const size_t nctr = ctr_words(1);
+    JZ_TRY(d_ctr.get(ac, nctr * sizeof(unsigned long long), s));
     JZ_TRY(d_uf.get(ac, n * sizeof(int), s));
     JZ_TRY(d_min.get(ac, n * sizeof(int), s));
     unsigned long long *ctr = d_ctr.as<unsigned long long>();
@@ -422,23 +431,23 @@ jz_status run_fof(jz_tree *t, const float *b2_set_host, int32_t *label, hipStrea
             const int *whole_par = top ? nullptr : whole[p + 1].as<int>();
             const int64_t n_par = top ? t->S : t->L[p + 1];
             const float *bn = sets ? b2n[p].as<float>() : nullptr;
-            k_fof_p2n<<<blocks_for(n_par, 4), 256, 0, s>>>(par_spl, t->nodes[p].as<Node>(),
+            k_fof_p2n<<<blocks_for(n_par, WPB), 64 * WPB, 0, s>>>(par_spl, t->nodes[p].as<Node>(),
                                                            (int)n_par, whole_par,
                                                            whole[p].as<int>(), d_uf.as<int>(), b2,
                                                            bn);
-            k_fof_step<<<blocks_for(n_par, 4), 256, 0, s>>>(
+            k_fof_step<<<blocks_for(n_par, WPB), 64 * WPB, 0, s>>>(
                 seg_in, list_in, par_spl, t->nodes[p].as<Node>(), (int)n_par, b2, bn,
                 whole[p].as<int>(), d_uf.as<int>(), segs[p].as<int2>(), lists[p].as<int2>(),
-                ctr + p, cap[p]);
+                ctr + (size_t)p * LIST_ARENAS, cap[p] / LIST_ARENAS, ctr + CTR_FLAG);
         }
-        k_fof_l2p<<<blocks_for(t->L[0], 4), 256, 0, s>>>(t->nodes[0].as<Node>(), (int)t->L[0],
+        k_fof_l2p<<<blocks_for(t->L[0], WPB), 64 * WPB, 0, s>>>(t->nodes[0].as<Node>(), (int)t->L[0],
                                                          whole[0].as<int>(), d_uf.as<int>());
         JZ_HIP(hipGetLastError());
         if (ev.on) JZ_HIP(hipEventRecord(ev[1], s));
-        k_leaf_fof<<<blocks_for(t->L[0], 4), 256, 0, s>>>(
+        k_leaf_fof<<<blocks_for(t->L[0], WPB), 64 * WPB, 0, s>>>(
             segs[0].as<int2>(), lists[0].as<int2>(), t->nodes[0].as<Node>(), t->pts4.as<float4>(),
             (int)t->L[0], b2, sets ? b2n[0].as<float>() : nullptr, whole[0].as<int>(),
-            d_uf.as<int>(), ctr + JZ_MAX_PLANES);
+            d_uf.as<int>(), ctr + CTR_STATS, ctr + CTR_FLAG);
         if (ev.on) JZ_HIP(hipEventRecord(ev[2], s));
         k_flatten_min<<<blocks_for(n, 256), 256, 0, s>>>(d_uf.as<int>(), t->pts4.as<float4>(), n,
                                                           d_min.as<int>());
@@ -447,17 +456,20 @@ jz_status run_fof(jz_tree *t, const float *b2_set_host, int32_t *label, hipStrea
                                                      t->nsets, label);
         JZ_HIP(hipGetLastError());
         if (ev.on) JZ_HIP(hipEventRecord(ev[3], s));
-        unsigned long long hc[JZ_MAX_PLANES + 4];
-        JZ_HIP(hipMemcpyAsync(hc, ctr, sizeof(hc), hipMemcpyDeviceToHost, s));
+        std::vector<unsigned long long> hc(nctr);
+        JZ_HIP(hipMemcpyAsync(hc.data(), ctr, nctr * sizeof(unsigned long long),
+                              hipMemcpyDeviceToHost, s));
         JZ_HIP(hipStreamSynchronize(s));
         bool overflow = false;
+        double sum[JZ_MAX_PLANES], need[JZ_MAX_PLANES];
         for (int p = 0; p < P; ++p) {
-            if ((int64_t)hc[p] <= cap[p]) continue;
+            arena_need(hc.data(), p, sum[p], need[p]);
+            if (need[p] <= (double)(cap[p] / LIST_ARENAS * LIST_ARENAS)) continue;
             overflow = true;
-            if ((int64_t)hc[p] > INT32_MAX)
-                return jz_fail(JZ_E_CAPACITY, "FoF list at plane %d needs %llu entries "
-                               "(more than 2^31-1)", p, (unsigned long long)hc[p]);
-            const double want = (double)hc[p] * 1.15 + 1024.0;
+            if (need[p] > (double)INT32_MAX)
+                return jz_fail(JZ_E_CAPACITY, "FoF list at plane %d needs %.0f entries "
+                               "(more than 2^31-1)", p, need[p]);
+            const double want = need[p] * 1.15 + 1024.0;
             cap[p] = want > (double)INT32_MAX ? (int64_t)INT32_MAX : (int64_t)want;
         }
         if (overflow) {
@@ -467,11 +479,11 @@ jz_status run_fof(jz_tree *t, const float *b2_set_host, int32_t *label, hipStrea
             continue;
         }
         for (int p = 0; p < P; ++p) {
-            t->st.list_entries[p] = (int64_t)hc[p];
-            cap_learn(CAP_FOF, 0, p, (double)hc[p] / (double)std::max<int64_t>(1, t->L[p]));
+            t->st.list_entries[p] = (int64_t)sum[p];
+            cap_learn(CAP_FOF, 0, p, need[p] / (double)std::max<int64_t>(1, t->L[p]));
         }
         t->st.leaf_pairs = t->st.list_entries[0];
-        t->st.evaluations = (double)hc[JZ_MAX_PLANES];
+        t->st.evaluations = stat_sum(hc.data(), 0);
         if (ev.on) {
             float ms = 0;
             JZ_HIP(hipEventElapsedTime(&ms, ev[1], ev[2]));

@@ -178,7 +178,11 @@ __device__ __forceinline__ void uf_union(int *par, int a, int b) {
 // sparse regions spreads evenly over the XCDs (one contiguous range per XCD
 // leaves the XCD with the densest range finishing last). Workgroups past the
 // last complete round of runs take one contiguous range per XCD.
-constexpr int XCD_RUN = 4;
+// Kernels that give each work item one wave run WPB waves per workgroup. A
+// workgroup keeps its registers and LDS until its slowest wave ends, so with
+// waves of uneven cost one wave per workgroup keeps the most waves resident.
+constexpr int WPB = 1;
+constexpr int XCD_RUN = 16 / WPB;
 __device__ __forceinline__ int xcd_block(int bid, int nblocks) {
     constexpr int per = 8 * XCD_RUN;
     const int full = nblocks / per;

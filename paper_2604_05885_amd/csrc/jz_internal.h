@@ -157,6 +157,37 @@ struct EventSet {
     hipEvent_t operator[](int i) const { return e[i]; }
 };
 
+// Device counters of one walk: [0, JZ_MAX_PLANES) list entries per level,
+// [CTR_FLAG] the overflow flag, and from CTR_STATS the leaf-stage statistics,
+// each spread over STAT_SLOTS words (a wave adds into slot item % STAT_SLOTS:
+// one address shared by every wave serializes the adds in L2 and slows the
+// kernel) and summed on the host.
+constexpr int STAT_SLOTS = 256;
+// Interaction-list space of a level is split into LIST_ARENAS arenas, each
+// with its own fill counter: a wave reserves its segment in arena
+// (receiver parent % LIST_ARENAS), which spreads the reservation atomics.
+constexpr int LIST_ARENAS = 64;
+constexpr int CTR_FLAG = JZ_MAX_PLANES * LIST_ARENAS;
+constexpr int CTR_STATS = CTR_FLAG + 8;
+inline size_t ctr_words(int nstats) { return (size_t)CTR_STATS + (size_t)nstats * STAT_SLOTS; }
+// Entries a level asked for: the sum over its arenas, and the size every
+// arena must have (the fullest arena times the arena count).
+inline void arena_need(const unsigned long long *hc, int level, double &sum, double &need) {
+    unsigned long long tot = 0, mx = 0;
+    for (int a = 0; a < LIST_ARENAS; ++a) {
+        const unsigned long long v = hc[(size_t)level * LIST_ARENAS + a];
+        tot += v;
+        mx = v > mx ? v : mx;
+    }
+    sum = (double)tot;
+    need = (double)mx * LIST_ARENAS;
+}
+inline double stat_sum(const unsigned long long *hc, int i) {
+    unsigned long long v = 0;
+    for (int j = 0; j < STAT_SLOTS; ++j) v += hc[CTR_STATS + (size_t)i * STAT_SLOTS + j];
+    return (double)v;
+}
+
 // launch helpers
 inline unsigned blocks_for(int64_t items, int per_block) {
     int64_t b = (items + per_block - 1) / per_block;

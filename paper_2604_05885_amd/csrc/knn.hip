@@ -185,16 +185,16 @@ __device__ __forceinline__ void for_source_batches(bool staged, const uint64_t *
 //   pass 2  count pairs with d_low^2 <= R
 //   pass 3  insert them (with r_low = d_low^2) at offsets reserved with one
 //           atomic per wave; a child's entries are contiguous.
-__global__ __launch_bounds__(256) void k_knn_step(
+__global__ __launch_bounds__(64 * WPB) void k_knn_step(
     const int2 *__restrict__ seg_in, const int2 *__restrict__ list_in,
     const int *__restrict__ par_spl, const Node *__restrict__ nodes, int n_par, int k,
     int2 *__restrict__ seg_out, int2 *__restrict__ list_out,
-    unsigned long long *__restrict__ ctr, long long cap) {
-    __shared__ uint64_t s_list[4][LCAP];
-    __shared__ Node s_f[4][FCAP];
-    __shared__ int s_fi[4][FCAP];
-    const int w = uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
-    const int P = xcd_block(blockIdx.x, gridDim.x) * 4 + w;
+    unsigned long long *__restrict__ ctr, long long cap, unsigned long long *overflow) {
+    __shared__ uint64_t s_list[WPB][LCAP];
+    __shared__ Node s_f[WPB][FCAP];
+    __shared__ int s_fi[WPB][FCAP];
+    const int w = WPB == 1 ? 0 : uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+    const int P = xcd_block(blockIdx.x, gridDim.x) * WPB + w;
     if (P >= n_par) return;
     const int2 sg = seg_in[P];
     const int2 *gl = list_in + uni(sg.x);
@@ -276,10 +276,16 @@ __global__ __launch_bounds__(256) void k_knn_step(
         // reserve: lanes are child-major, so a wave scan gives contiguous segments
         const int incl = wave_incl_scan(cnt);
         const int total = uni(__shfl(incl, 63, 64));
-        unsigned long long base = 0;
-        if (lane == 0) base = atomicAdd(ctr, (unsigned long long)total);
-        base = uni((unsigned long long)__shfl(base, 0, 64));
-        const bool ok = (long long)base + total <= cap;
+        // segment in arena P % LIST_ARENAS (cap entries each)
+        const int ar = P & (LIST_ARENAS - 1);
+        unsigned long long lb = 0;
+        if (lane == 0) lb = atomicAdd(ctr + ar, (unsigned long long)total);
+        lb = uni((unsigned long long)__shfl(lb, 0, 64));
+        const unsigned long long base = (unsigned long long)ar * (unsigned long long)cap + lb;
+        const bool ok = (long long)lb + total <= cap;
+        // an overflowing level makes every list below it incomplete: flag it,
+        // so that the leaf stage of this attempt exits at once
+        if (!ok && lane == 0) *overflow = 1;
         const int gfirst = (ci << lg), glast = gfirst + G - 1;
         const int gstart = __shfl(incl - cnt, gfirst & 63, 64);
         const int gend = __shfl(incl, glast & 63, 64);
@@ -483,19 +489,21 @@ __device__ __forceinline__ void merge_chunk(TopK<K> &a, const double (&ch)[C]) {
 // inserted into the register top-k in rounds, so insert time follows the
 // busiest lane rather than every accepted candidate of any lane.
 template <int K>
-__global__ __launch_bounds__(256) void k_leaf_knn(
+__global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
     const int2 *__restrict__ seg, const int2 *__restrict__ list, const Node *__restrict__ leaves,
     const float4 *__restrict__ pts, int n_leaves, const int *__restrict__ leaf_base,
     int32_t *__restrict__ out_idx, float *__restrict__ out_d2,
-    unsigned long long *__restrict__ stats) {
-    __shared__ uint64_t s_list[4][LCAP];
-    __shared__ float4 s_tile[4][TILE_PTS];
-    __shared__ Node s_nodes[4][SB];
-    __shared__ int s_offs[4][SB + 1];
-    __shared__ uint8_t s_q[4][CQ][64];
-    const int w = uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
-    const int A = xcd_block(blockIdx.x, gridDim.x) * 4 + w;
-    if (A >= n_leaves) return;
+    unsigned long long *__restrict__ stats, const unsigned long long *__restrict__ overflow) {
+    __shared__ uint64_t s_list[WPB][LCAP];
+    __shared__ float4 s_tile[WPB][TILE_PTS];
+    __shared__ Node s_nodes[WPB][SB];
+    __shared__ int s_offs[WPB][SB + 1];
+    __shared__ uint8_t s_q[WPB][CQ][64];
+    __shared__ float4 s_box[WPB][TILE_PTS / 8 * 2];  // (lo, hi) of every 8 tile positions
+    const int w = WPB == 1 ? 0 : uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+    const int A = xcd_block(blockIdx.x, gridDim.x) * WPB + w;
+    // a level of this attempt overflowed (it is rerun): nothing to do
+    if (A >= n_leaves || *overflow) return;
     const Node a = leaves[A];
     const int acount = uni(a.count);
     const int lgS = acount <= 16 ? 2 : (acount <= 32 ? 1 : 0);  // log2 lanes per query
@@ -508,6 +516,7 @@ __global__ __launch_bounds__(256) void k_leaf_knn(
     const int len = uni(sg.y);
     uint64_t *L = s_list[w];
     float4 *tile = s_tile[w];
+    float4 *cbox = s_box[w];
     Node *nb = s_nodes[w];
     int *offs = s_offs[w];
     const bool staged = len <= LCAP;
@@ -536,15 +545,20 @@ __global__ __launch_bounds__(256) void k_leaf_knn(
         // a scalar trip count (a loop on a ballot compiles to a divergent
         // loop, whose exit handling copies the list every round)
         const int nr = uni(wave_max_int(qn));
+        // The candidate of round c + 1 is read while round c inserts (its two
+        // dependent LDS reads would otherwise stall every round). Slots are
+        // read unconditionally: a branch around a read would make the
+        // compiler copy the list every round.
+        float4 s = tile[0 < qn ? q0[0] : 0];
         for (int c = 0; c < nr; ++c) {
             ++rounds;
             const bool has = c < qn;
-            // the slot is read unconditionally (a branch around the read
-            // would make the compiler copy the list every round)
-            const int qv = q0[64 * c];
-            const float4 s = tile[has ? qv : 0];
-            const float dd = dist2_pts(me.x, me.y, me.z, s.x, s.y, s.z);
-            const double key = key_of(dd, __float_as_int(s.w));
+            const float4 cur = s;
+            const int cn = c + 1 < CQ ? c + 1 : c;
+            const int qv = q0[64 * cn];
+            s = tile[cn < qn ? qv : 0];
+            const float dd = dist2_pts(me.x, me.y, me.z, cur.x, cur.y, cur.z);
+            const double key = key_of(dd, __float_as_int(cur.w));
             topk_insert<K>(best, has ? key : pad);
         }
         qp = q0;
@@ -593,8 +607,8 @@ __global__ __launch_bounds__(256) void k_leaf_knn(
         for (int o = 32; o > 0; o >>= 1) any |= __shfl_xor(any, o, 64);
         any = uni(any);
         // take needed sources in order while their points fit the tile; each
-        // occupies a multiple of S positions (every lane computes the same
-        // offsets; lane 0 keeps them in LDS for the scan)
+        // occupies a multiple of 8 positions, one box per 8 (every lane
+        // computes the same offsets; lane 0 keeps them in LDS for the scan)
         int take = 0, npts = 0;
         int o_r[SB + 1];
         o_r[0] = 0;
@@ -602,7 +616,7 @@ __global__ __launch_bounds__(256) void k_leaf_knn(
 #pragma unroll
         for (int qq = 0; qq < SB; ++qq) {
             const bool want = qq < nb_n && take == qq;
-            const int c = want && ((any >> qq) & 1u) ? (uni(nb[qq].count) + S - 1) & -S : 0;
+            const int c = want && ((any >> qq) & 1u) ? (uni(nb[qq].count) + 7) & -8 : 0;
             if (want && npts + c <= TILE_PTS) {
                 npts += c;
                 take = qq + 1;
@@ -610,17 +624,38 @@ __global__ __launch_bounds__(256) void k_leaf_knn(
             o_r[qq + 1] = npts;
             if (lane == 0) offs[qq + 1] = npts;
         }
-        // stage the taken sources' points (one loop per source; the loads are
-        // independent). Filler positions hold a point at +inf with index -1:
-        // its key is the padding key, so accepting it changes nothing.
+        // stage the taken sources' points (lane f takes point f of a source:
+        // a leaf holds at most 64 points) and the bounding box of every 8
+        // positions (reduced over groups of 8 lanes). Filler positions hold a
+        // point at +inf with index -1: its key is the padding key, so
+        // accepting it changes nothing; it is left out of the boxes.
 #pragma unroll
         for (int qq = 0; qq < SB; ++qq) {
             if (qq < take && o_r[qq + 1] > o_r[qq]) {
                 const int cnt = uni(nb[qq].count), st = uni(nb[qq].start);
-                for (int f = lane; f < o_r[qq + 1] - o_r[qq]; f += 64)
-                    tile[o_r[qq] + f] = f < cnt ? pts[st + f]
-                                                : make_float4(INFINITY, INFINITY, INFINITY,
-                                                              __int_as_float(-1));
+                const int size = o_r[qq + 1] - o_r[qq];
+                const bool real = lane < cnt;
+                float4 p = make_float4(INFINITY, INFINITY, INFINITY, __int_as_float(-1));
+                if (real) p = pts[st + lane];
+                if (lane < size) tile[o_r[qq] + lane] = p;
+                float lx = real ? p.x : INFINITY, ly = real ? p.y : INFINITY,
+                      lz = real ? p.z : INFINITY;
+                float hx = real ? p.x : -INFINITY, hy = real ? p.y : -INFINITY,
+                      hz = real ? p.z : -INFINITY;
+#pragma unroll
+                for (int o = 1; o < 8; o <<= 1) {
+                    lx = fminf(lx, __shfl_xor(lx, o, 64));
+                    ly = fminf(ly, __shfl_xor(ly, o, 64));
+                    lz = fminf(lz, __shfl_xor(lz, o, 64));
+                    hx = fmaxf(hx, __shfl_xor(hx, o, 64));
+                    hy = fmaxf(hy, __shfl_xor(hy, o, 64));
+                    hz = fmaxf(hz, __shfl_xor(hz, o, 64));
+                }
+                if ((lane & 7) == 0 && lane < size) {
+                    float4 *bx = cbox + ((o_r[qq] + lane) >> 3) * 2;
+                    bx[0] = make_float4(lx, ly, lz, 0.0f);
+                    bx[1] = make_float4(hx, hy, hz, 0.0f);
+                }
             }
         }
         // next window
@@ -663,13 +698,25 @@ __global__ __launch_bounds__(256) void k_leaf_knn(
                 ++visited;
                 const bool need = (needbits >> qq) & 1u;
                 const int f0 = uni(offs[qq]), f1 = uni(offs[qq + 1]);
-                for (int j0 = f0; j0 < f1; j0 += CH * SS) {
-                    const int j1 = min(f1, j0 + CH * SS);
-                    // a lane whose query cannot reach this source accepts nothing
-                    const float thr = need ? kth : -1.0f;
-#pragma unroll 4
-                    for (int jj = j0; jj < j1; jj += SS) {
-                        const int j = jj + h;
+                const int cnt = uni(nb[qq].count);
+                for (int j0 = f0; j0 < f1; j0 += 8) {
+                    // 8 positions with their box: skipped when no lane's query
+                    // can reach the box; a lane that cannot accepts nothing
+                    const float4 *bx = cbox + (j0 >> 3) * 2;
+                    const float4 blo = bx[0], bhi = bx[1];
+                    const float gx = fmaxf(fmaxf(blo.x - me.x, me.x - bhi.x), 0.0f);
+                    const float gy = fmaxf(fmaxf(blo.y - me.y, me.y - bhi.y), 0.0f);
+                    const float gz = fmaxf(fmaxf(blo.z - me.z, me.z - bhi.z), 0.0f);
+                    const float xx = gx * gx;
+                    const float yy = gy * gy;
+                    const float zz = gz * gz;
+                    const float sxy = xx + yy;
+                    const bool cneed = need && sxy + zz <= kth;
+                    if (!__ballot(cneed)) continue;
+                    const float thr = cneed ? kth : -1.0f;
+#pragma unroll 2
+                    for (int u = 0; u < 8 / SS; ++u) {
+                        const int j = j0 + u * SS + h;
                         const float4 p = tile[j];
                         const float dd = dist2_pts(me.x, me.y, me.z, p.x, p.y, p.z);
                         // written always, kept only if accepted (at most CH
@@ -677,15 +724,15 @@ __global__ __launch_bounds__(256) void k_leaf_knn(
                         *qp = (uint8_t)j;
                         qp += dd <= thr ? 64 : 0;
                     }
-                    steps += (unsigned)((j1 - j0) / SS);
+                    steps += (unsigned)(8 / SS);
+                    if (cneed) {
+                        const int r = min(8, cnt - (j0 - f0));
+                        evals += r > h ? (unsigned)((r - h + SS - 1) / SS) : 0u;
+                    }
                     if (__ballot(qp > qlim)) {
                         drain();
                         kth = group_kth();
                     }
-                }
-                if (need) {
-                    const int cnt = uni(nb[qq].count);
-                    evals += cnt > h ? (unsigned)((cnt - h + SS - 1) / SS) : 0u;
                 }
             }
         };
@@ -724,15 +771,16 @@ __global__ __launch_bounds__(256) void k_leaf_knn(
     }
     const int ev = wave_sum((int)evals);
     if (lane == 0) {
-        atomicAdd(stats + 0, (unsigned long long)ev);
-        atomicAdd(stats + 1, (unsigned long long)visited);
-        atomicAdd(stats + 2, (unsigned long long)rounds);
-        atomicAdd(stats + 3, (unsigned long long)steps);
+        unsigned long long *st = stats + (A & (STAT_SLOTS - 1));
+        atomicAdd(st + 0 * STAT_SLOTS, (unsigned long long)ev);
+        atomicAdd(st + 1 * STAT_SLOTS, (unsigned long long)visited);
+        atomicAdd(st + 2 * STAT_SLOTS, (unsigned long long)rounds);
+        atomicAdd(st + 3 * STAT_SLOTS, (unsigned long long)steps);
     }
 }
 
 typedef void (*leaf_fn)(const int2 *, const int2 *, const Node *, const float4 *, int, const int *,
-                        int32_t *, float *, unsigned long long *);
+                        int32_t *, float *, unsigned long long *, const unsigned long long *);
 
 template <int K>
 leaf_fn leaf_ptr() {
@@ -764,9 +812,11 @@ jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s) 
     t->st.insert_rounds = t->st.tile_steps = 0;
     if (t->n == 0) return JZ_OK;
 
-    // counters: [0, P) list entries per level, [JZ_MAX_PLANES, +2) leaf stats
+    // counters: four leaf statistics (evaluations, sources visited, insert
+    // rounds, tile steps)
     DBuf d_ctr;
-    JZ_TRY(d_ctr.get(ac, (JZ_MAX_PLANES + 4) * sizeof(unsigned long long), s));
+    const size_t nctr = ctr_words(4);
+    JZ_TRY(d_ctr.get(ac, nctr * sizeof(unsigned long long), s));
     unsigned long long *ctr = d_ctr.as<unsigned long long>();
     JZ_HIP(hipMemsetAsync(ctr, 0, d_ctr.bytes, s));
     int64_t cap[JZ_MAX_PLANES];
@@ -790,54 +840,59 @@ jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s) 
             const int2 *list_in = top ? t->knn_top_list.as<int2>() : lists[p + 1].as<int2>();
             const int *par_spl = top ? t->super_spl.as<int>() : t->spl[p + 1].as<int>();
             const int64_t n_par = top ? t->S : t->L[p + 1];
-            k_knn_step<<<blocks_for(n_par, 4), 256, 0, s>>>(seg_in, list_in, par_spl,
+            k_knn_step<<<blocks_for(n_par, WPB), 64 * WPB, 0, s>>>(seg_in, list_in, par_spl,
                                                             t->nodes[p].as<Node>(), (int)n_par, k,
                                                             segs[p].as<int2>(), lists[p].as<int2>(),
-                                                            ctr + p, cap[p]);
+                                                            ctr + (size_t)p * LIST_ARENAS,
+                                                            cap[p] / LIST_ARENAS, ctr + CTR_FLAG);
         }
         JZ_HIP(hipGetLastError());
         if (ev.on) JZ_HIP(hipEventRecord(ev[1], s));
-        leaf_kernel(k)<<<blocks_for(t->L[0], 4), 256, 0, s>>>(
+        leaf_kernel(k)<<<blocks_for(t->L[0], WPB), 64 * WPB, 0, s>>>(
             segs[0].as<int2>(), lists[0].as<int2>(), t->nodes[0].as<Node>(), t->pts4.as<float4>(),
             (int)t->L[0], t->nsets > 1 ? t->leaf_base.as<int>() : nullptr, idx, dist2,
-            ctr + JZ_MAX_PLANES);
+            ctr + CTR_STATS, ctr + CTR_FLAG);
         JZ_HIP(hipGetLastError());
         if (ev.on) JZ_HIP(hipEventRecord(ev[2], s));
-        unsigned long long hc[JZ_MAX_PLANES + 4];
-        JZ_HIP(hipMemcpyAsync(hc, ctr, sizeof(hc), hipMemcpyDeviceToHost, s));
+        std::vector<unsigned long long> hc(nctr);
+        JZ_HIP(hipMemcpyAsync(hc.data(), ctr, nctr * sizeof(unsigned long long),
+                              hipMemcpyDeviceToHost, s));
         JZ_HIP(hipStreamSynchronize(s));
         int redo = -1;
+        double sum[JZ_MAX_PLANES], need[JZ_MAX_PLANES];
+        for (int p = P - 1; p >= 0; --p) arena_need(hc.data(), p, sum[p], need[p]);
         for (int p = start; p >= 0; --p) {
-            if ((int64_t)hc[p] <= cap[p]) continue;
-            if ((int64_t)hc[p] > INT32_MAX)
-                return jz_fail(JZ_E_CAPACITY, "interaction list at plane %d needs %llu entries "
-                               "(more than 2^31-1)", p, (unsigned long long)hc[p]);
+            if (need[p] <= (double)(cap[p] / LIST_ARENAS * LIST_ARENAS)) continue;
+            if (need[p] > (double)INT32_MAX)
+                return jz_fail(JZ_E_CAPACITY, "interaction list at plane %d needs %.0f entries "
+                               "(more than 2^31-1)", p, need[p]);
             if (redo < 0) redo = p;
-            const double want = (double)hc[p] * 1.15 + 1024.0;
+            const double want = need[p] * 1.15 + 1024.0;
             cap[p] = want > (double)INT32_MAX ? (int64_t)INT32_MAX : (int64_t)want;
         }
         if (redo >= 0) {
             if (!t->opts.auto_regrow)
                 return jz_fail(JZ_E_CAPACITY,
                                "interaction list overflow at plane %d; list_per_node must be at "
-                               "least %.1f", redo, (double)hc[redo] / (double)t->L[redo]);
+                               "least %.1f", redo, need[redo] / (double)t->L[redo]);
             t->st.reruns++;
             start = redo;
-            // clear the counters of the levels to redo and the leaf statistics
-            for (int p = 0; p <= start; ++p) hc[p] = 0;
-            JZ_HIP(hipMemcpyAsync(ctr, hc, sizeof(hc), hipMemcpyHostToDevice, s));
-            JZ_HIP(hipMemsetAsync(ctr + JZ_MAX_PLANES, 0, 4 * sizeof(unsigned long long), s));
+            // clear the counters of the levels to redo, the flag and the leaf
+            // statistics
+            JZ_HIP(hipMemsetAsync(ctr, 0, (size_t)(start + 1) * LIST_ARENAS * sizeof(unsigned long long), s));
+            JZ_HIP(hipMemsetAsync(ctr + CTR_FLAG, 0,
+                                  (nctr - CTR_FLAG) * sizeof(unsigned long long), s));
             continue;
         }
         for (int p = 0; p < P; ++p) {
-            t->st.list_entries[p] = (int64_t)hc[p];
-            cap_learn(CAP_KNN, k, p, (double)hc[p] / (double)std::max<int64_t>(1, t->L[p]));
+            t->st.list_entries[p] = (int64_t)sum[p];
+            cap_learn(CAP_KNN, k, p, need[p] / (double)std::max<int64_t>(1, t->L[p]));
         }
         t->st.leaf_pairs = t->st.list_entries[0];
-        t->st.evaluations = (double)hc[JZ_MAX_PLANES];
-        t->st.leaf_pairs_visited = (int64_t)hc[JZ_MAX_PLANES + 1];
-        t->st.insert_rounds = (int64_t)hc[JZ_MAX_PLANES + 2];
-        t->st.tile_steps = (int64_t)hc[JZ_MAX_PLANES + 3];
+        t->st.evaluations = stat_sum(hc.data(), 0);
+        t->st.leaf_pairs_visited = (int64_t)stat_sum(hc.data(), 1);
+        t->st.insert_rounds = (int64_t)stat_sum(hc.data(), 2);
+        t->st.tile_steps = (int64_t)stat_sum(hc.data(), 3);
         if (ev.on) {
             float ms = 0;
             JZ_HIP(hipEventElapsedTime(&ms, ev[1], ev[2]));
