@@ -82,6 +82,93 @@ __device__ __forceinline__ float uni(float v) {
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
 
+// Cross-lane reductions without LDS round trips: DPP permutations inside
+// each row of 16 lanes (xor 1, xor 2, the mirror inside 8 lanes and inside 16
+// lanes pair every lane with a partner until the row is combined), then the
+// gfx950 row swaps (lanes l and l ^ 16, then l and l ^ 32). Every lane ends
+// with the reduction over the wave (or over the stated group). All lanes of
+// the wave must be active.
+constexpr int DPP_XOR1 = 0xB1;         // quad_perm [1, 0, 3, 2]
+constexpr int DPP_XOR2 = 0x4E;         // quad_perm [2, 3, 0, 1]
+constexpr int DPP_HALF_MIRROR = 0x141; // lane i <-> 7 - i inside each 8
+constexpr int DPP_MIRROR = 0x140;      // lane i <-> 15 - i inside each 16
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, true);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+    return __int_as_float(dpp_i<CTRL>(__float_as_int(v)));
+}
+// the value of lane l ^ 16 (a) and of lane l ^ 32 (b)
+__device__ __forceinline__ int swap16_i(int v) {
+    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    return (__lane_id() & 16) ? r[0] : r[1];
+}
+__device__ __forceinline__ int swap32_i(int v) {
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return (__lane_id() & 32) ? r[0] : r[1];
+}
+__device__ __forceinline__ float swap16_f(float v) { return __int_as_float(swap16_i(__float_as_int(v))); }
+__device__ __forceinline__ double swap16_d(double v) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint64_t lo = (uint32_t)swap16_i((int)(uint32_t)b), hi = (uint32_t)swap16_i((int)(b >> 32));
+    return __builtin_bit_cast(double, (hi << 32) | lo);
+}
+__device__ __forceinline__ double swap32_d(double v) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint64_t lo = (uint32_t)swap32_i((int)(uint32_t)b), hi = (uint32_t)swap32_i((int)(b >> 32));
+    return __builtin_bit_cast(double, (hi << 32) | lo);
+}
+__device__ __forceinline__ float swap32_f(float v) { return __int_as_float(swap32_i(__float_as_int(v))); }
+
+// reduction over each group of 8 lanes (lanes 8g .. 8g + 7)
+__device__ __forceinline__ float group8_min(float v) {
+    v = fminf(v, dpp_f<DPP_XOR1>(v));
+    v = fminf(v, dpp_f<DPP_XOR2>(v));
+    return fminf(v, dpp_f<DPP_HALF_MIRROR>(v));
+}
+__device__ __forceinline__ float group8_max(float v) {
+    v = fmaxf(v, dpp_f<DPP_XOR1>(v));
+    v = fmaxf(v, dpp_f<DPP_XOR2>(v));
+    return fmaxf(v, dpp_f<DPP_HALF_MIRROR>(v));
+}
+// wave-wide reductions (result in every lane)
+__device__ __forceinline__ int wave_max_i(int v) {
+    v = max(v, dpp_i<DPP_XOR1>(v));
+    v = max(v, dpp_i<DPP_XOR2>(v));
+    v = max(v, dpp_i<DPP_HALF_MIRROR>(v));
+    v = max(v, dpp_i<DPP_MIRROR>(v));
+    v = max(v, swap16_i(v));
+    return max(v, swap32_i(v));
+}
+__device__ __forceinline__ float wave_max_f(float v) {
+    v = fmaxf(v, dpp_f<DPP_XOR1>(v));
+    v = fmaxf(v, dpp_f<DPP_XOR2>(v));
+    v = fmaxf(v, dpp_f<DPP_HALF_MIRROR>(v));
+    v = fmaxf(v, dpp_f<DPP_MIRROR>(v));
+    v = fmaxf(v, swap16_f(v));
+    return fmaxf(v, swap32_f(v));
+}
+__device__ __forceinline__ unsigned wave_or(unsigned v) {
+    int x = (int)v;
+    x |= dpp_i<DPP_XOR1>(x);
+    x |= dpp_i<DPP_XOR2>(x);
+    x |= dpp_i<DPP_HALF_MIRROR>(x);
+    x |= dpp_i<DPP_MIRROR>(x);
+    x |= swap16_i(x);
+    x |= swap32_i(x);
+    return (unsigned)x;
+}
+__device__ __forceinline__ int wave_sum_i(int v) {
+    v += dpp_i<DPP_XOR1>(v);
+    v += dpp_i<DPP_XOR2>(v);
+    v += dpp_i<DPP_HALF_MIRROR>(v);
+    v += dpp_i<DPP_MIRROR>(v);
+    v += swap16_i(v);
+    return v + swap32_i(v);
+}
+
 __device__ __forceinline__ float wave_max(float v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));

@@ -535,8 +535,8 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
     // the group's k-th distance: an upper bound of the query's final k-th
     auto group_kth = [&]() {
         float v = key_dist(best.get(K - 1));
-        if (lgS >= 1) v = fminf(v, __shfl_xor(v, 32, 64));
-        if (lgS >= 2) v = fminf(v, __shfl_xor(v, 16, 64));
+        if (lgS >= 1) v = fminf(v, swap32_f(v));
+        if (lgS >= 2) v = fminf(v, swap16_f(v));
         return v;
     };
     // insert the queued candidates of every lane into its top-k
@@ -544,7 +544,7 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
         const int qn = (int)(qp - q0) >> 6;
         // a scalar trip count (a loop on a ballot compiles to a divergent
         // loop, whose exit handling copies the list every round)
-        const int nr = uni(wave_max_int(qn));
+        const int nr = uni(wave_max_i(qn));
         // The candidate of round c + 1 is read while round c inserts (its two
         // dependent LDS reads would otherwise stall every round). Slots are
         // read unconditionally: a branch around a read would make the
@@ -586,7 +586,7 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
     int t = 0;
     while (t < len) {
         float kth = group_kth();
-        const float Rw = uni(wave_max(act ? kth : -INFINITY));
+        const float Rw = uni(wave_max_f(act ? kth : -INFINITY));
         // sources t .. t + nb_n - 1 of this batch: the window's entries with
         // r_low <= Rw (a prefix, the list being sorted by r_low)
         const bool inb = pf_ok && (!staged || pf_rl <= Rw);
@@ -602,10 +602,7 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
         unsigned needbits = 0;
         for (int qq = 0; qq < nb_n; ++qq)
             if (act && point_box_low2(me, nb[qq]) <= kth) needbits |= 1u << qq;
-        unsigned any = needbits;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) any |= __shfl_xor(any, o, 64);
-        any = uni(any);
+        const unsigned any = uni(wave_or(needbits));
         // take needed sources in order while their points fit the tile; each
         // occupies a multiple of 8 positions, one box per 8 (every lane
         // computes the same offsets; lane 0 keeps them in LDS for the scan)
@@ -642,15 +639,12 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
                       lz = real ? p.z : INFINITY;
                 float hx = real ? p.x : -INFINITY, hy = real ? p.y : -INFINITY,
                       hz = real ? p.z : -INFINITY;
-#pragma unroll
-                for (int o = 1; o < 8; o <<= 1) {
-                    lx = fminf(lx, __shfl_xor(lx, o, 64));
-                    ly = fminf(ly, __shfl_xor(ly, o, 64));
-                    lz = fminf(lz, __shfl_xor(lz, o, 64));
-                    hx = fmaxf(hx, __shfl_xor(hx, o, 64));
-                    hy = fmaxf(hy, __shfl_xor(hy, o, 64));
-                    hz = fmaxf(hz, __shfl_xor(hz, o, 64));
-                }
+                lx = group8_min(lx);
+                ly = group8_min(ly);
+                lz = group8_min(lz);
+                hx = group8_max(hx);
+                hy = group8_max(hy);
+                hz = group8_max(hz);
                 if ((lane & 7) == 0 && lane < size) {
                     float4 *bx = cbox + ((o_r[qq] + lane) >> 3) * 2;
                     bx[0] = make_float4(lx, ly, lz, 0.0f);
@@ -714,7 +708,7 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
                     const bool cneed = need && sxy + zz <= kth;
                     if (!__ballot(cneed)) continue;
                     const float thr = cneed ? kth : -1.0f;
-#pragma unroll 2
+#pragma unroll 4
                     for (int u = 0; u < 8 / SS; ++u) {
                         const int j = j0 + u * SS + h;
                         const float4 p = tile[j];
@@ -747,13 +741,13 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
     if (lgS >= 1) {
         TopK<K> other;
 #pragma unroll
-        for (int i = 0; i < K; ++i) other.set(i, __shfl_xor(best.get(i), 32, 64));
+        for (int i = 0; i < K; ++i) other.set(i, swap32_d(best.get(i)));
         merge_topk<K>(best, other);
     }
     if (lgS >= 2) {
         TopK<K> other;
 #pragma unroll
-        for (int i = 0; i < K; ++i) other.set(i, __shfl_xor(best.get(i), 16, 64));
+        for (int i = 0; i < K; ++i) other.set(i, swap16_d(best.get(i)));
         merge_topk<K>(best, other);
     }
     if (act && h == 0) {
@@ -769,7 +763,7 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
             od[r] = none ? INFINITY : __uint_as_float((uint32_t)(e >> 32));
         }
     }
-    const int ev = wave_sum((int)evals);
+    const int ev = wave_sum_i((int)evals);
     if (lane == 0) {
         unsigned long long *st = stats + (A & (STAT_SLOTS - 1));
         atomicAdd(st + 0 * STAT_SLOTS, (unsigned long long)ev);
