@@ -245,9 +245,7 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_fof(
         for (int q = 0; q < nb_n; ++q)
             if (!((skipmask >> q) & 1u) && act && point_box_low2_f(me, nb[q]) <= bb)
                 needbits |= 1u << q;
-        unsigned any = needbits;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) any |= __shfl_xor(any, o, 64);
+        unsigned any = wave_or(needbits);
         any = uni(any);
         int take = 0, npts = 0;
         if (lane == 0) offs[0] = 0;
@@ -315,7 +313,7 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_fof(
         wave_lds_sync();
         t += take;
     }
-    const int ev = wave_sum((int)evals);
+    const int ev = wave_sum_i((int)evals);
     if (lane == 0) atomicAdd(stats + (A & (STAT_SLOTS - 1)), (unsigned long long)ev);
 }
 
@@ -343,12 +341,10 @@ __global__ __launch_bounds__(256) void k_flatten_min(int *__restrict__ uf,
     uint64_t pending = __ballot(valid);
     while (pending) {
         const int leader = __ffsll((unsigned long long)pending) - 1;
-        const int r0 = __shfl(root, leader, 64);
+        const int r0 = __builtin_amdgcn_readlane(root, leader);
         const bool mine = valid && root == r0;
         const uint64_t m = __ballot(mine);
-        int vm = mine ? v : INT_MAX;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) vm = min(vm, __shfl_xor(vm, o, 64));
+        const int vm = wave_min_i(mine ? v : INT_MAX);
         if (lane_id() == leader) atomicMin(minidx + r0, vm);
         pending &= ~m;
     }

@@ -150,6 +150,24 @@ __device__ __forceinline__ float wave_max_f(float v) {
     v = fmaxf(v, swap16_f(v));
     return fmaxf(v, swap32_f(v));
 }
+__device__ __forceinline__ int wave_min_i(int v) {
+    v = min(v, dpp_i<DPP_XOR1>(v));
+    v = min(v, dpp_i<DPP_XOR2>(v));
+    v = min(v, dpp_i<DPP_HALF_MIRROR>(v));
+    v = min(v, dpp_i<DPP_MIRROR>(v));
+    v = min(v, swap16_i(v));
+    return min(v, swap32_i(v));
+}
+// minimum over each aligned group of G lanes (G a power of 2, wave-uniform)
+__device__ __forceinline__ float group_min_f(float v, int G) {
+    if (G >= 2) v = fminf(v, dpp_f<DPP_XOR1>(v));
+    if (G >= 4) v = fminf(v, dpp_f<DPP_XOR2>(v));
+    if (G >= 8) v = fminf(v, dpp_f<DPP_HALF_MIRROR>(v));
+    if (G >= 16) v = fminf(v, dpp_f<DPP_MIRROR>(v));
+    if (G >= 32) v = fminf(v, swap16_f(v));
+    if (G >= 64) v = fminf(v, swap32_f(v));
+    return v;
+}
 __device__ __forceinline__ unsigned wave_or(unsigned v) {
     int x = (int)v;
     x |= dpp_i<DPP_XOR1>(x);

@@ -227,7 +227,7 @@ __global__ __launch_bounds__(64 * WPB) void k_knn_step(
         // pass 1: FindRmax over this lane's slice
         for_source_batches(
             staged, L, gl, len, par_spl, nodes, F, FI,
-            [&]() { return wave_max(act ? R : -INFINITY); },
+            [&]() { return wave_max_f(act ? R : -INFINITY); },
             [&](int nF) {
                 for (int f = sl; f < nF; f += G) {
                     const Node o = F[f];
@@ -261,11 +261,11 @@ __global__ __launch_bounds__(64 * WPB) void k_knn_step(
                     if (acc >= k) best = re;
                 }
             }
-            for (int o = 1; o < G; o <<= 1) best = fminf(best, __shfl_xor(best, o, 64));
+            best = group_min_f(best, G);
             R = best;
             wave_lds_sync();
         }
-        const float Rw = uni(wave_max(act ? R : -INFINITY));
+        const float Rw = uni(wave_max_f(act ? R : -INFINITY));
         // pass 2: count
         int cnt = 0;
         for_source_batches(
