@@ -191,9 +191,11 @@ __device__ __forceinline__ float point_box_low2_f(const float4 &q, const Node &b
 // (leaves B >= A) are read in batches of FSB Node records. A source is
 // skipped when A and B are both whole and already one group; a lane skips a
 // source its point cannot reach (point-to-box bound > b^2); the points of the
-// sources some lane needs are staged together in LDS. Per source, every lane
-// first records which of its points link to its own point (no atomics);
-// only if some lane links are the roots of the source's points looked up, in
+// sources some lane needs are staged together in LDS, each source padded to
+// a multiple of 8 positions, with the bounding box of every 8 positions; 8
+// positions no lane can reach are skipped. Per source, every lane first
+// records which of its points link to its own point (no atomics); only if
+// some lane links are the roots of the source's points looked up, in
 // parallel, and unions made where the roots differ (a lane's own root is
 // cached; groups only ever merge, so equal roots, even looked up at different
 // times, mean already connected). Two whole leaves need only one link.
@@ -203,6 +205,7 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_fof(
     const int *__restrict__ whole, int *__restrict__ uf, unsigned long long *__restrict__ stats,
     const unsigned long long *__restrict__ overflow) {
     __shared__ float4 s_tile[WPB][FTILE];
+    __shared__ float4 s_box[WPB][FTILE / 8 * 2];  // (lo, hi) of every 8 tile positions
     __shared__ Node s_nodes[WPB][FSB];
     __shared__ int s_offs[WPB][FSB + 1];
     __shared__ int s_root[WPB][64];
@@ -221,6 +224,7 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_fof(
     const int2 *gl = list + uni(sg.x);
     const int len = uni(sg.y);
     float4 *tile = s_tile[w];
+    float4 *cbox = s_box[w];
     Node *nb = s_nodes[w];
     int *offs = s_offs[w];
     int *rootT = s_root[w];
@@ -245,22 +249,46 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_fof(
         for (int q = 0; q < nb_n; ++q)
             if (!((skipmask >> q) & 1u) && act && point_box_low2_f(me, nb[q]) <= bb)
                 needbits |= 1u << q;
-        unsigned any = wave_or(needbits);
-        any = uni(any);
+        const unsigned any = uni(wave_or(needbits));
+        // take needed sources in order while their (8-padded) points fit
         int take = 0, npts = 0;
+        int o_r[FSB + 1];
+        o_r[0] = 0;
         if (lane == 0) offs[0] = 0;
-        for (int q = 0; q < nb_n; ++q) {
-            const int c = (any >> q) & 1u ? uni(nb[q].count) : 0;
-            if (npts + c > FTILE) break;
-            npts += c;
+#pragma unroll
+        for (int q = 0; q < FSB; ++q) {
+            const bool want = q < nb_n && take == q;
+            const int c = want && ((any >> q) & 1u) ? (uni(nb[q].count) + 7) & -8 : 0;
+            if (want && npts + c <= FTILE) {
+                npts += c;
+                take = q + 1;
+            }
+            o_r[q + 1] = npts;
             if (lane == 0) offs[q + 1] = npts;
-            take = q + 1;
         }
-        wave_lds_sync();
-        for (int f = lane; f < npts; f += 64) {
-            int q = 0;
-            while (offs[q + 1] <= f) ++q;
-            tile[f] = pts[nb[q].start + (f - offs[q])];
+        // stage points (lane f takes point f of a source) and 8-position
+        // boxes; fillers lie at +inf (never within b) and stay out of boxes
+#pragma unroll
+        for (int q = 0; q < FSB; ++q) {
+            if (q < take && o_r[q + 1] > o_r[q]) {
+                const int cnt = uni(nb[q].count), st = uni(nb[q].start);
+                const int size = o_r[q + 1] - o_r[q];
+                const bool real = lane < cnt;
+                float4 p = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
+                if (real) p = pts[st + lane];
+                if (lane < size) tile[o_r[q] + lane] = p;
+                const float lx = group8_min(real ? p.x : INFINITY);
+                const float ly = group8_min(real ? p.y : INFINITY);
+                const float lz = group8_min(real ? p.z : INFINITY);
+                const float hx = group8_max(real ? p.x : -INFINITY);
+                const float hy = group8_max(real ? p.y : -INFINITY);
+                const float hz = group8_max(real ? p.z : -INFINITY);
+                if ((lane & 7) == 0 && lane < size) {
+                    float4 *bx = cbox + ((o_r[q] + lane) >> 3) * 2;
+                    bx[0] = make_float4(lx, ly, lz, 0.0f);
+                    bx[1] = make_float4(hx, hy, hz, 0.0f);
+                }
+            }
         }
         wave_lds_sync();
         for (int q = 0; q < take; ++q) {
@@ -268,16 +296,32 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_fof(
             const bool need = (needbits >> q) & 1u;
             const bool wB = (wholemask >> q) & 1u;
             const int f0 = uni(offs[q]), f1 = uni(offs[q + 1]);
-            const int b0 = uni(nb[q].start);
-            // 1: which points of this source link to this lane's point
+            const int b0 = uni(nb[q].start), cnt = uni(nb[q].count);
+            // 1: which points of this source link to this lane's point (a
+            // point links to the later points of the pair only)
             uint64_t lm = 0;
-            if (need) {
-                for (int f = f0; f < f1; ++f) {
-                    const float4 s = tile[f];
-                    if (b0 + (f - f0) > my && dist2_pts(me.x, me.y, me.z, s.x, s.y, s.z) <= bb)
-                        lm |= 1ull << (f - f0);
+            for (int j0 = f0; j0 < f1; j0 += 8) {
+                const float4 *bx = cbox + (j0 >> 3) * 2;
+                const float4 blo = bx[0], bhi = bx[1];
+                const float gx = fmaxf(fmaxf(blo.x - me.x, me.x - bhi.x), 0.0f);
+                const float gy = fmaxf(fmaxf(blo.y - me.y, me.y - bhi.y), 0.0f);
+                const float gz = fmaxf(fmaxf(blo.z - me.z, me.z - bhi.z), 0.0f);
+                const float xx = gx * gx;
+                const float yy = gy * gy;
+                const float zz = gz * gz;
+                const float sxy = xx + yy;
+                const bool cneed = need && sxy + zz <= bb;
+                if (!__ballot(cneed)) continue;
+                const int first = b0 + (j0 - f0);  // point index of position j0
+                unsigned m8 = 0;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const float4 s = tile[j0 + u];
+                    const float dd = dist2_pts(me.x, me.y, me.z, s.x, s.y, s.z);
+                    m8 |= (cneed && first + u > my && dd <= bb) ? (1u << u) : 0u;
                 }
-                evals += (unsigned)(f1 - f0);
+                lm |= (uint64_t)m8 << (j0 - f0);
+                if (cneed) evals += (unsigned)min(8, cnt - (j0 - f0));
             }
             const uint64_t linking = __ballot(lm != 0);
             if (!linking) continue;
@@ -291,7 +335,7 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_fof(
             int rB = -1;
             if (wB) {
                 rB = uf_find(uf, b0);
-            } else if (lane < f1 - f0) {
+            } else if (lane < cnt) {
                 rootT[lane] = uf_find(uf, b0 + lane);
             }
             wave_lds_sync();
