@@ -437,9 +437,11 @@ template <int K, int C>
 __device__ __forceinline__ void merge_chunk(TopK<K> &a, const double (&ch)[C]) {
     constexpr int M = next_pow2(K);
     if constexpr (M == K) {
-        // in place: only the last C entries meet a chunk key
+        // in place: only the last min(C, M) entries meet a chunk key (a
+        // chunk longer than the list contributes its M smallest keys)
 #pragma unroll
-        for (int i = M - C; i < M; ++i) a.set(i, __builtin_fmin(a.get(i), ch[M - 1 - i]));
+        for (int i = (M > C ? M - C : 0); i < M; ++i)
+            a.set(i, __builtin_fmin(a.get(i), ch[M - 1 - i]));
 #pragma unroll
         for (int d = M / 2; d > 0; d >>= 1) {
 #pragma unroll
@@ -539,27 +541,29 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
         if (lgS >= 2) v = fminf(v, swap16_f(v));
         return v;
     };
-    // insert the queued candidates of every lane into its top-k
+    // insert the queued candidates of every lane into its top-k: 8 at a time,
+    // sorted in registers and merged (the busiest lane sets the trip count,
+    // so batches of 8 cost far less than one insertion per candidate)
     auto drain = [&]() {
         const int qn = (int)(qp - q0) >> 6;
         // a scalar trip count (a loop on a ballot compiles to a divergent
         // loop, whose exit handling copies the list every round)
         const int nr = uni(wave_max_i(qn));
-        // The candidate of round c + 1 is read while round c inserts (its two
-        // dependent LDS reads would otherwise stall every round). Slots are
-        // read unconditionally: a branch around a read would make the
-        // compiler copy the list every round.
-        float4 s = tile[0 < qn ? q0[0] : 0];
-        for (int c = 0; c < nr; ++c) {
-            ++rounds;
-            const bool has = c < qn;
-            const float4 cur = s;
-            const int cn = c + 1 < CQ ? c + 1 : c;
-            const int qv = q0[64 * cn];
-            s = tile[cn < qn ? qv : 0];
-            const float dd = dist2_pts(me.x, me.y, me.z, cur.x, cur.y, cur.z);
-            const double key = key_of(dd, __float_as_int(cur.w));
-            topk_insert<K>(best, has ? key : pad);
+        for (int c = 0; c < nr; c += 8) {
+            rounds += 8;
+            double ch[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                // slots are read unconditionally (branches around the reads
+                // would make the compiler copy the list)
+                const int slot = min(c + u, CQ - 1);
+                const int qv = q0[64 * slot];
+                const float4 s = tile[c + u < qn ? qv : 0];
+                const float dd = dist2_pts(me.x, me.y, me.z, s.x, s.y, s.z);
+                ch[u] = c + u < qn ? key_of(dd, __float_as_int(s.w)) : pad;
+            }
+            sort_keys<8>(ch);
+            merge_chunk<K, 8>(best, ch);
         }
         qp = q0;
     };
