@@ -158,14 +158,16 @@ __device__ __forceinline__ void for_source_batches(bool staged, const uint64_t *
             nF = FCAP;
             skip += FCAP;
         } else {
+            // lane q < ntake lists the indices of its source's children;
+            // then every lane copies node records lane, lane + 64, ... (the
+            // loads are independent instead of one chain per source)
             if (lane < ntake) {
                 const int off = incl - c;
-                for (int q = 0; q < c; ++q) {
-                    F[off + q] = nodes[s0 + q];
-                    FI[off + q] = s0 + q;
-                }
+                for (int q = 0; q < c; ++q) FI[off + q] = s0 + q;
             }
             nF = uni(__shfl(incl, ntake - 1, 64));
+            wave_lds_sync();
+            for (int f = lane; f < nF; f += 64) F[f] = nodes[FI[f]];
             t += ntake;
             skip = 0;
         }
