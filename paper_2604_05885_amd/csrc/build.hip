@@ -316,32 +316,52 @@ constexpr int LF_MAXW = 64;
 // Leaf-plane split flags: gap g is a split iff the node spanning it holds
 // more than nmax0 points, i.e. the nearest strictly greater gap on one side
 // lies farther than the window, or both lie within it but r - l > nmax0.
+// The nearest greater gaps are found by binary lifting over a table of range
+// maxima of the tile (mx[k][i] = max of the 2^k levels from i), so every
+// thread takes the same ~2 x 7 steps instead of a scan of up to 2 x nmax0.
+constexpr int LF_SPAN = LF_TILE + 2 * LF_MAXW + 2;
+constexpr int LF_LOG = 7;  // 2^6 = LF_MAXW: levels 0..6
 __global__ __launch_bounds__(256) void k_leaf_flags(const uint64_t *__restrict__ keys, int64_t n,
                                                     int bits3, int has_sets, int nmax0,
                                                     uint8_t *__restrict__ flags,
                                                     int *__restrict__ blk_cnt) {
-    __shared__ uint8_t s_lv[LF_TILE + 2 * LF_MAXW + 2];
+    __shared__ uint8_t s_mx[LF_LOG][LF_SPAN];
     __shared__ int s_c[4];
     const int W = nmax0;
+    const int span = LF_TILE + 2 * W + 1;
     const int64_t g0 = (int64_t)blockIdx.x * LF_TILE;
-    for (int t = threadIdx.x; t < LF_TILE + 2 * W + 1; t += blockDim.x)
-        s_lv[t] = (uint8_t)gap_level(keys, n, g0 - W + t, bits3, has_sets);
+    for (int t = threadIdx.x; t < span; t += blockDim.x)
+        s_mx[0][t] = (uint8_t)gap_level(keys, n, g0 - W + t, bits3, has_sets);
     __syncthreads();
+    for (int k = 1; k < LF_LOG; ++k) {
+        const int h = 1 << (k - 1);
+        for (int t = threadIdx.x; t + 2 * h <= span; t += blockDim.x)
+            s_mx[k][t] = max(s_mx[k - 1][t], s_mx[k - 1][t + h]);
+        __syncthreads();
+    }
     int cnt = 0;
     for (int t = threadIdx.x; t < LF_TILE; t += blockDim.x) {
         const int64_t g = g0 + t;
         if (g > n) break;
-        const int lv = s_lv[t + W];
+        const int c = t + W;  // g's position in the tile
+        const int lv = s_mx[0][c];
         uint8_t f;
         if (lv >= kBoundaryLevel) {
             f = 1;
         } else {
-            int dl = 0, dr = 0;
-            for (int d = 1; d <= W; ++d)
-                if (s_lv[t + W - d] > lv) { dl = d; break; }
-            if (dl)
-                for (int d = 1; d <= W; ++d)
-                    if (s_lv[t + W + d] > lv) { dr = d; break; }
+            // left: move cur down while [cur - 2^k, cur) holds no greater level
+            int cur = c;
+            for (int k = LF_LOG - 1; k >= 0; --k)
+                if (cur - (1 << k) >= c - W && s_mx[k][cur - (1 << k)] <= lv) cur -= 1 << k;
+            const int dl = cur - 1 >= c - W ? c - (cur - 1) : 0;
+            int dr = 0;
+            if (dl) {
+                // right: move cur up while [cur, cur + 2^k) holds no greater level
+                cur = c + 1;
+                for (int k = LF_LOG - 1; k >= 0; --k)
+                    if (cur + (1 << k) - 1 <= c + W && s_mx[k][cur] <= lv) cur += 1 << k;
+                dr = cur <= c + W ? cur - c : 0;
+            }
             f = (dl == 0 || dr == 0 || dl + dr > nmax0) ? 1 : 0;
         }
         flags[g] = f;
