@@ -377,7 +377,7 @@ __device__ __forceinline__ float point_box_low2(const float4 &q, const Node &b) 
     return s + zz;
 }
 
-constexpr int SB = 8;         // source leaves examined per batch
+constexpr int SB = 16;        // source leaves examined per batch
 constexpr int TILE_PTS = 256; // source points staged per batch (positions fit a byte)
 constexpr int CQ = 32;        // queued candidate positions per lane
 constexpr int CH = 8;         // tile positions a lane scans between queue checks
