@@ -312,12 +312,16 @@ def served(args):
     torch.cuda.synchronize()
     print("# pool of %d sets (%d points) in %.1fs" % (args.pool, sum(q.shape[0] for q in pool),
                                                       time.time() - t0), file=sys.stderr, flush=True)
-    count = int(args.rate * args.duration)
-    reqs = inputs.served_requests(count, seed=5, rate_hz=args.rate)
-    for r in reqs:
-        r["set"] = int(rng.integers(args.pool))
+    def schedule(rate, duration, seed):
+        rs = inputs.served_requests(int(rate * duration), seed=seed, rate_hz=rate)
+        pick = np.random.default_rng(seed + 1)
+        for r in rs:
+            r["set"] = int(pick.integers(args.pool))
+        return rs
 
-    def run(streams, max_sets):
+    reqs = schedule(args.rate, args.duration, 5)
+
+    def run(streams, max_sets, reqs=reqs, measure_after=args.measure_after):
         S = api.Server(streams=streams, max_batch_sets=max_sets, hbm_budget=int(200e9))
         # warm the library (kernels, pool, learned list sizes)
         for q, o, l in zip(pool[:8], outs[:8], labs[:8]):
@@ -337,10 +341,17 @@ def served(args):
                                   labs[r["set"]])
             tickets.append((tk, due, r))
         lat, last_done, first_due, npts = [], 0, None, 0
+        failed, first_error = 0, None
         for tk, due, r in tickets:
-            _, done_ns = S.wait(tk)
+            try:
+                _, done_ns = S.wait(tk)
+            except api.JzError as e:  # reported, not hidden: a failed request is a bug
+                failed += 1
+                first_error = first_error or str(e)
+                S.release(tk)
+                continue
             S.release(tk)
-            if r["t"] >= args.measure_after:
+            if r["t"] >= measure_after:
                 lat.append((done_ns - due) / 1e6)
                 last_done = max(last_done, done_ns)
                 first_due = due if first_due is None else min(first_due, due)
@@ -352,10 +363,18 @@ def served(args):
         return {"solves_per_s": len(lat) / span, "points_per_s": npts / span,
                 "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                 "requests": len(lat), "batches": st["batches"],
-                "max_batch": st["max_batch_sets_seen"]}
+                "max_batch": st["max_batch_sets_seen"], "failed": failed,
+                "first_error": first_error}
 
     cont = run(args.streams, 4096)
     fifo = run(1, 1)
+    # When the offered rate exceeds what the device sustains, the queue grows
+    # for the whole run and p50/p99 measure that backlog; so the server is
+    # also run at 60% of the solves/s it sustained, where latency is service
+    # time plus batching delay.
+    light_rate = 0.6 * cont["solves_per_s"]
+    light = run(args.streams, 4096, reqs=schedule(light_rate, 6.0, 7), measure_after=1.0)
+    light["offered_req_per_s"] = light_rate
     out = {
         "metric": "served kNN/FoF solves/s with p50/p99 latency (open-loop Poisson arrivals)",
         "value": cont["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
@@ -367,6 +386,7 @@ def served(args):
                                % (args.rate, args.duration, args.measure_after, args.pool)},
         "continuous_batching": cont,
         "per_request_fifo": fifo,
+        "continuous_batching_at_60pct_of_sustained": light,
         "speedup_vs_fifo": cont["solves_per_s"] / fifo["solves_per_s"],
     }
     print(json.dumps(out), flush=True)

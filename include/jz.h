@@ -190,7 +190,8 @@ JZ_API jz_status jz_server_submit(jz_server *s, const jz_request *r, uint64_t *t
 
 /* *done = 1 once the request's outputs are complete on the device; then
  * *result holds its status and *done_ns the completion time on the clock of
- * jz_now_ns(). Any output pointer may be NULL. */
+ * jz_now_ns(). Any output pointer may be NULL. When the request failed, its
+ * error message becomes the calling thread's jz_last_error(). */
 JZ_API jz_status jz_server_poll(jz_server *s, uint64_t ticket, int *done, jz_status *result,
                                 int64_t *done_ns);
 

@@ -17,6 +17,7 @@
 #include <deque>
 #include <mutex>
 #include <new>
+#include <string>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -37,6 +38,7 @@ struct Req {
     size_t bytes = 0;
     bool done = false;
     jz_status status = JZ_OK;
+    std::string msg;  // the worker's error message when status != JZ_OK
     int64_t t_done = 0;
 };
 
@@ -211,6 +213,7 @@ void worker(jz_server *S) {
         lk.unlock();
         const jz_status rs = stream ? run_batch(S, batch, stream)
                                     : jz_fail(JZ_E_DEVICE, "no HIP stream for this worker");
+        const std::string err = rs == JZ_OK ? std::string() : std::string(jz_last_error());
         lk.lock();
         S->in_use -= bytes;
         S->st.in_flight_bytes = (int64_t)S->in_use;
@@ -218,6 +221,7 @@ void worker(jz_server *S) {
         for (Req *q : batch) {
             q->done = true;
             q->status = rs;
+            q->msg = err;
             q->t_done = t;
             if (rs == JZ_OK) {
                 S->st.completed++;
@@ -316,6 +320,8 @@ jz_status jz_server_poll(jz_server *S, uint64_t ticket, int *done, jz_status *re
     if (q->done) {
         if (result) *result = q->status;
         if (done_ns) *done_ns = q->t_done;
+        // the failed request's message becomes this thread's last error
+        if (q->status != JZ_OK) (void)jz_fail(q->status, "%s", q->msg.c_str());
     }
     return JZ_OK;
 }
@@ -328,6 +334,7 @@ jz_status jz_server_wait(jz_server *S, uint64_t ticket, jz_status *result, int64
     Req *q = it->second;
     S->cv_done.wait(lk, [&] { return q->done; });
     if (result) *result = q->status;
+    if (q->status != JZ_OK) (void)jz_fail(q->status, "%s", q->msg.c_str());
     if (done_ns) *done_ns = q->t_done;
     return JZ_OK;
 }
