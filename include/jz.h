@@ -235,6 +235,9 @@ typedef struct jz_stats {
     int reruns;                      /* capacity reruns in the last call */
     int64_t insert_rounds;           /* kNN leaf stage: wave-level top-k insert rounds */
     int64_t tile_steps;              /* kNN leaf stage: wave-level candidate steps */
+    int64_t lists_sorted_long;       /* kNN leaf stage: lists longer than the 256 entries staged in
+                                        LDS, sorted through the wave's scratch (<= 1024 entries) */
+    int64_t lists_unordered;         /* kNN leaf stage: lists longer than that, read unordered */
 } jz_stats;
 
 /* Statistics of the tree and of its last kNN / FoF call. */
@@ -259,7 +262,7 @@ JZ_API void jz_release_cached(void);
 /* Thread-local message of the last error (empty string if none). */
 JZ_API const char *jz_last_error(void);
 
-/* ABI version of this header (1). */
+/* ABI version of this header (2). */
 JZ_API int jz_abi_version(void);
 
 #ifdef __cplusplus

@@ -43,7 +43,8 @@ class Stats(ctypes.Structure):
                 ("leaf_pairs", ctypes.c_int64), ("leaf_pairs_visited", ctypes.c_int64),
                 ("evaluations", ctypes.c_double), ("leaf_ms", ctypes.c_double),
                 ("total_ms", ctypes.c_double), ("reruns", ctypes.c_int),
-                ("insert_rounds", ctypes.c_int64), ("tile_steps", ctypes.c_int64)]
+                ("insert_rounds", ctypes.c_int64), ("tile_steps", ctypes.c_int64),
+                ("lists_sorted_long", ctypes.c_int64), ("lists_unordered", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         P = self.planes
@@ -53,7 +54,9 @@ class Stats(ctypes.Structure):
                 "leaf_pairs": self.leaf_pairs, "leaf_pairs_visited": self.leaf_pairs_visited,
                 "evaluations": self.evaluations, "leaf_ms": self.leaf_ms,
                 "total_ms": self.total_ms, "reruns": self.reruns,
-                "insert_rounds": self.insert_rounds, "tile_steps": self.tile_steps}
+                "insert_rounds": self.insert_rounds, "tile_steps": self.tile_steps,
+                "lists_sorted_long": self.lists_sorted_long,
+                "lists_unordered": self.lists_unordered}
 
 
 class Allocator(ctypes.Structure):

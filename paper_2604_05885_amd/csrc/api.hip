@@ -387,6 +387,6 @@ void jz_release_cached(void) {
 
 const char *jz_last_error(void) { return g_err.c_str(); }
 
-int jz_abi_version(void) { return 1; }
+int jz_abi_version(void) { return 2; }
 
 }  // extern "C"

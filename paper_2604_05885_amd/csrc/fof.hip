@@ -424,6 +424,7 @@ jz_status run_fof(jz_tree *t, const float *b2_set_host, int32_t *label, hipStrea
     t->st.leaf_ms = t->st.total_ms = 0;
     t->st.reruns = 0;
     t->st.insert_rounds = t->st.tile_steps = 0;
+    t->st.lists_sorted_long = t->st.lists_unordered = 0;
     if (n == 0) return JZ_OK;
 
     const bool sets = t->nsets > 1;

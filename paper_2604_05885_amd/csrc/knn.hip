@@ -27,6 +27,11 @@
 namespace {
 
 constexpr int LCAP = 256;  // list entries staged (and sorted) in LDS per wave
+constexpr int prev_pow2(int x) {
+    int m = 1;
+    while (m * 2 <= x) m *= 2;
+    return m;
+}
 constexpr uint64_t PAD_KEY = (0x7f800000ull << 32) | 0xffffffffull;  // (+inf, no index)
 
 __device__ __forceinline__ uint64_t list_key(int2 e) {
@@ -56,9 +61,41 @@ __device__ void stage_sorted(const int2 *__restrict__ src, int len, uint64_t *L)
     }
 }
 
+// Order a receiver's list by (r_low, source). A list of at most LCAP entries
+// is staged in L. A longer one, of at most scap entries, is sorted in the
+// LDS scratch that begins with L (the wave's other buffers, not yet in use)
+// and written back whole, in order, over its segment in HBM (the segment
+// belongs to this receiver alone); its first LCAP entries stay in L. The
+// segment stays a permutation of the list, so a level that is run again
+// after a capacity overflow reads the same list. Either way the list then
+// reads in r_low order and the walk can stop at the first entry beyond its
+// radius. Returns false (list left as it is, read unordered) when the list
+// exceeds scap.
+__device__ bool stage_list(int2 *__restrict__ gl, int len, uint64_t *S, int scap) {
+    if (len > scap) return false;
+    stage_sorted(gl, len, S);
+    if (len > LCAP) {
+        for (int i = lane_id(); i < len; i += 64) {
+            const uint64_t e = S[i];
+            gl[i] = make_int2((int)(uint32_t)e, (int)(uint32_t)(e >> 32));
+        }
+        // the wave reads entries from LCAP on back later, from other lanes:
+        // wait until the stores have reached L2 (the wave's own, so this
+        // CU's L2) and drop this CU's vector L1, which may still hold the
+        // lines as they were loaded above. (A workgroup-scope fence compiles
+        // to nothing in a one-wave workgroup; an agent-scope one would also
+        // write back and invalidate L2, which the other XCDs never read.)
+        __asm__ volatile("s_waitcnt vmcnt(0)\n\tbuffer_inv sc0" ::: "memory");
+    }
+    wave_lds_sync();
+    return true;
+}
+
+// Entry t of a receiver's list: from LDS for the first LCAP entries of an
+// ordered list, else from HBM.
 __device__ __forceinline__ void list_entry(bool staged, const uint64_t *L, const int2 *g, int t,
                                            int &src, float &rl) {
-    if (staged) {
+    if (staged && t < LCAP) {
         const uint64_t e = L[t];
         src = (int)(uint32_t)e;
         rl = __uint_as_float((uint32_t)(e >> 32));
@@ -188,25 +225,27 @@ __device__ __forceinline__ void for_source_batches(bool staged, const uint64_t *
 //   pass 3  insert them (with r_low = d_low^2) at offsets reserved with one
 //           atomic per wave; a child's entries are contiguous.
 __global__ __launch_bounds__(64 * WPB) void k_knn_step(
-    const int2 *__restrict__ seg_in, const int2 *__restrict__ list_in,
+    const int2 *__restrict__ seg_in, int2 *__restrict__ list_in,
     const int *__restrict__ par_spl, const Node *__restrict__ nodes, int n_par, int k,
     int2 *__restrict__ seg_out, int2 *__restrict__ list_out,
-    unsigned long long *__restrict__ ctr, long long cap, unsigned long long *overflow) {
-    __shared__ uint64_t s_list[WPB][LCAP];
-    __shared__ Node s_f[WPB][FCAP];
-    __shared__ int s_fi[WPB][FCAP];
+    unsigned long long *__restrict__ ctr, long long cap, unsigned long long *overflow,
+    bool sort_long) {
+    // one block per wave: the staged list (LCAP entries), then the staged
+    // source children (FCAP records and their indices); before the walk the
+    // whole block is the scratch in which a longer list is sorted
+    constexpr int RAW = LCAP + FCAP * (int)(sizeof(Node) / 8) + FCAP / 2;
+    __shared__ __align__(16) uint64_t s_raw[WPB][RAW];
     const int w = WPB == 1 ? 0 : uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
     const int P = xcd_block(blockIdx.x, gridDim.x) * WPB + w;
     if (P >= n_par) return;
     const int2 sg = seg_in[P];
-    const int2 *gl = list_in + uni(sg.x);
+    int2 *gl = list_in + uni(sg.x);
     const int len = uni(sg.y);
     const int c0 = uni(par_spl[P]), c1 = uni(par_spl[P + 1]);
-    uint64_t *L = s_list[w];
-    Node *F = s_f[w];
-    int *FI = s_fi[w];
-    const bool staged = len <= LCAP;
-    if (staged) stage_sorted(gl, len, L);
+    uint64_t *L = s_raw[w];
+    Node *F = reinterpret_cast<Node *>(L + LCAP);
+    int *FI = reinterpret_cast<int *>(L + LCAP + FCAP * (int)(sizeof(Node) / 8));
+    const bool staged = stage_list(gl, len, L, sort_long ? prev_pow2(RAW) : LCAP);
 
     for (int cb = c0; cb < c1; cb += 64) {
         const int nc = min(64, c1 - cb);
@@ -236,9 +275,12 @@ __global__ __launch_bounds__(64 * WPB) void k_knn_step(
                     const float r = box_up2(me, o);
                     if (act && r < R) {
                         heap_insert<NR_HEAP>(hr, hc, r, o.count);
-                        R = radius_of_count<NR_HEAP>(hr, hc, k);
+                        R = fminf(R, radius_of_count<NR_HEAP>(hr, hc, k));
                     }
                 }
+                // each lane's radius already bounds its child (k points of its
+                // slice lie within it), so the child's lanes share the smallest
+                R = group_min_f(R, G);
             });
         if (G > 1) {
             // exact merge of the G heaps of each child (LDS scratch: F's buffer)
@@ -264,7 +306,7 @@ __global__ __launch_bounds__(64 * WPB) void k_knn_step(
                 }
             }
             best = group_min_f(best, G);
-            R = best;
+            R = fminf(best, R);
             wave_lds_sync();
         }
         const float Rw = uni(wave_max_f(act ? R : -INFINITY));
@@ -494,16 +536,19 @@ __device__ __forceinline__ void merge_chunk(TopK<K> &a, const double (&ch)[C]) {
 // busiest lane rather than every accepted candidate of any lane.
 template <int K>
 __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
-    const int2 *__restrict__ seg, const int2 *__restrict__ list, const Node *__restrict__ leaves,
+    const int2 *__restrict__ seg, int2 *__restrict__ list, const Node *__restrict__ leaves,
     const float4 *__restrict__ pts, int n_leaves, const int *__restrict__ leaf_base,
     int32_t *__restrict__ out_idx, float *__restrict__ out_d2,
     unsigned long long *__restrict__ stats, const unsigned long long *__restrict__ overflow) {
-    __shared__ uint64_t s_list[WPB][LCAP];
-    __shared__ float4 s_tile[WPB][TILE_PTS];
+    // one block per wave: the staged list (LCAP entries), the point tile,
+    // the (lo, hi) box of every 8 tile positions and the candidate queues;
+    // before the walk the whole block is the scratch in which a longer list
+    // is sorted
+    constexpr int O_TILE = LCAP, O_BOX = O_TILE + TILE_PTS * 2, O_Q = O_BOX + TILE_PTS / 8 * 4;
+    constexpr int RAW = O_Q + CQ * 64 / 8;
+    __shared__ __align__(16) uint64_t s_raw[WPB][RAW];
     __shared__ Node s_nodes[WPB][SB];
     __shared__ int s_offs[WPB][SB + 1];
-    __shared__ uint8_t s_q[WPB][CQ][64];
-    __shared__ float4 s_box[WPB][TILE_PTS / 8 * 2];  // (lo, hi) of every 8 tile positions
     const int w = WPB == 1 ? 0 : uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
     const int A = xcd_block(blockIdx.x, gridDim.x) * WPB + w;
     // a level of this attempt overflowed (it is rerun): nothing to do
@@ -516,15 +561,14 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
     const bool act = q < acount;
     const float4 me = pts[a.start + (act ? q : 0)];
     const int2 sg = seg[A];
-    const int2 *gl = list + uni(sg.x);
+    int2 *gl = list + uni(sg.x);
     const int len = uni(sg.y);
-    uint64_t *L = s_list[w];
-    float4 *tile = s_tile[w];
-    float4 *cbox = s_box[w];
+    uint64_t *L = s_raw[w];
+    float4 *tile = reinterpret_cast<float4 *>(L + O_TILE);
+    float4 *cbox = reinterpret_cast<float4 *>(L + O_BOX);
     Node *nb = s_nodes[w];
     int *offs = s_offs[w];
-    const bool staged = len <= LCAP;
-    if (staged) stage_sorted(gl, len, L);
+    const bool staged = stage_list(gl, len, L, prev_pow2(RAW));
 
     const double pad = __builtin_bit_cast(double, PAD_KEY);
     TopK<K> best;
@@ -532,7 +576,7 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
     for (int i = 0; i < K; ++i) best.set(i, pad);
     unsigned evals = 0, visited = 0, rounds = 0, steps = 0;
     // candidate queue of this lane: positions at q0, q0 + 64, ... up to qp
-    uint8_t *const q0 = &s_q[w][0][lane];
+    uint8_t *const q0 = reinterpret_cast<uint8_t *>(L + O_Q) + lane;
     uint8_t *qp = q0;
     const uint8_t *const qlim = q0 + 64 * (CQ - CH);
 
@@ -776,10 +820,11 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
         atomicAdd(st + 1 * STAT_SLOTS, (unsigned long long)visited);
         atomicAdd(st + 2 * STAT_SLOTS, (unsigned long long)rounds);
         atomicAdd(st + 3 * STAT_SLOTS, (unsigned long long)steps);
+        if (len > LCAP) atomicAdd(st + (staged ? 4 : 5) * STAT_SLOTS, 1ull);
     }
 }
 
-typedef void (*leaf_fn)(const int2 *, const int2 *, const Node *, const float4 *, int, const int *,
+typedef void (*leaf_fn)(const int2 *, int2 *, const Node *, const float4 *, int, const int *,
                         int32_t *, float *, unsigned long long *, const unsigned long long *);
 
 template <int K>
@@ -810,12 +855,13 @@ jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s) 
     t->st.leaf_ms = t->st.total_ms = 0;
     t->st.reruns = 0;
     t->st.insert_rounds = t->st.tile_steps = 0;
+    t->st.lists_sorted_long = t->st.lists_unordered = 0;
     if (t->n == 0) return JZ_OK;
 
     // counters: four leaf statistics (evaluations, sources visited, insert
     // rounds, tile steps)
     DBuf d_ctr;
-    const size_t nctr = ctr_words(4);
+    const size_t nctr = ctr_words(6);
     JZ_TRY(d_ctr.get(ac, nctr * sizeof(unsigned long long), s));
     unsigned long long *ctr = d_ctr.as<unsigned long long>();
     JZ_HIP(hipMemsetAsync(ctr, 0, d_ctr.bytes, s));
@@ -837,14 +883,17 @@ jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s) 
         for (int p = start; p >= 0; --p) {
             const bool top = p == P - 1;
             const int2 *seg_in = top ? t->knn_top_seg.as<int2>() : segs[p + 1].as<int2>();
-            const int2 *list_in = top ? t->knn_top_list.as<int2>() : lists[p + 1].as<int2>();
+            // the super-node list belongs to the tree (shared by every call):
+            // it is never written, so long lists there are read unordered
+            int2 *list_in = top ? t->knn_top_list.as<int2>() : lists[p + 1].as<int2>();
             const int *par_spl = top ? t->super_spl.as<int>() : t->spl[p + 1].as<int>();
             const int64_t n_par = top ? t->S : t->L[p + 1];
             k_knn_step<<<blocks_for(n_par, WPB), 64 * WPB, 0, s>>>(seg_in, list_in, par_spl,
                                                             t->nodes[p].as<Node>(), (int)n_par, k,
                                                             segs[p].as<int2>(), lists[p].as<int2>(),
                                                             ctr + (size_t)p * LIST_ARENAS,
-                                                            cap[p] / LIST_ARENAS, ctr + CTR_FLAG);
+                                                            cap[p] / LIST_ARENAS, ctr + CTR_FLAG,
+                                                            !top);
         }
         JZ_HIP(hipGetLastError());
         if (ev.on) JZ_HIP(hipEventRecord(ev[1], s));
@@ -893,6 +942,8 @@ jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s) 
         t->st.leaf_pairs_visited = (int64_t)stat_sum(hc.data(), 1);
         t->st.insert_rounds = (int64_t)stat_sum(hc.data(), 2);
         t->st.tile_steps = (int64_t)stat_sum(hc.data(), 3);
+        t->st.lists_sorted_long = (int64_t)stat_sum(hc.data(), 4);
+        t->st.lists_unordered = (int64_t)stat_sum(hc.data(), 5);
         if (ev.on) {
             float ms = 0;
             JZ_HIP(hipEventElapsedTime(&ms, ev[1], ev[2]));

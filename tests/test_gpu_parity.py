@@ -90,6 +90,26 @@ def test_knn_tree_shapes(jz, leaf_max, k):
     assert_knn_equal(gi, gd, wi, wd, "leaf_max=%d" % leaf_max)
 
 
+def test_knn_long_lists(jz):
+    """Leaves of at most 8 points in dense clumps with k = 32: many leaf lists
+    are longer than the 256 entries staged in LDS. Those of at most 1024 are
+    sorted through the wave's scratch and partly read back from HBM, longer
+    ones are read unordered; both kinds must occur, and the whole result must
+    equal the exact kd-tree oracle."""
+    p = inputs.clustered(60000, 16, 21)
+    gi, gd, st = gpu_knn(jz, p, 32, leaf_max=8)
+    assert st["lists_sorted_long"] > 0 and st["lists_unordered"] > 0, st
+    wi, wd = oracle.knn_kd(p, 32)
+    assert_knn_equal(gi, gd, wi, wd, "long lists")
+    # the same with list capacities far too small: levels are run again and
+    # read lists that their first attempt already sorted in place (k = 31,
+    # used by no other test, so no learned capacity applies; its exact
+    # result is the first 31 columns of the k = 32 one)
+    gi, gd, st = gpu_knn(jz, p, 31, leaf_max=8, list_per_node=1.0)
+    assert st["reruns"] >= 1 and st["lists_sorted_long"] > 0, st
+    assert_knn_equal(gi, gd, wi[:, :31], wd[:, :31], "long lists, rerun")
+
+
 def test_knn_capacity_regrow_same_result(jz):
     # k = 13 is used by no other test, so no learned capacity applies yet
     p = inputs.clustered(8000, 8, 22)
