@@ -154,7 +154,8 @@ constexpr int FCAP = 128;  // source children staged per batch
 // records in F, their indices in FI) until FCAP children; a source with more
 // children than FCAP is split over several batches. Sources whose r_low
 // exceeds rw() (re-evaluated per batch) end the walk. fn(nF) then processes
-// the nF staged children.
+// the nF staged children. The list entries of the next batch and their
+// children ranges are loaded while fn runs on the current one.
 template <class RW, class FN>
 __device__ __forceinline__ void for_source_batches(bool staged, const uint64_t *L,
                                                    const int2 *gl, int len,
@@ -163,34 +164,39 @@ __device__ __forceinline__ void for_source_batches(bool staged, const uint64_t *
                                                    RW &&rw, FN &&fn) {
     const int lane = lane_id();
     int t = 0, skip = 0;
-    while (t < len) {
-        const float Rw = uni(rw());
-        int src = 0, s0 = 0, cnt = 0;
-        float rl = 0.0f;
-        const bool valid = t + lane < len;
+    // entry t + lane of the list: its r_low and the range of its children
+    bool valid = false;
+    int s0 = 0, cnt = 0;
+    float rl = 0.0f;
+    auto load = [&](int t0) {
+        valid = t0 + lane < len;
         if (valid) {
-            list_entry(staged, L, gl, t + lane, src, rl);
+            int src;
+            list_entry(staged, L, gl, t0 + lane, src, rl);
             s0 = par_spl[src];
             cnt = par_spl[src + 1] - s0;
-            if (lane == 0) {
-                s0 += skip;
-                cnt -= skip;
-            }
         }
+    };
+    load(0);
+    while (t < len) {
+        const float Rw = uni(rw());
+        const int b0 = s0 + (lane == 0 ? skip : 0);
+        const int c_all = cnt - (lane == 0 ? skip : 0);
         const bool ok = valid && (!staged || rl <= Rw);
         const uint64_t okm = __ballot(ok);  // sorted by r_low: a prefix of the lanes
         const int nok = ~okm ? __ffsll((unsigned long long)~okm) - 1 : 64;
         if (nok == 0) break;
-        const int c = lane < nok ? cnt : 0;
+        const int c = lane < nok ? c_all : 0;
         const int incl = wave_incl_scan(c);
         const int ntake = __popcll(__ballot(lane < nok && incl <= FCAP));
         int nF;
         if (ntake == 0) {
-            // the first source alone overflows the buffer: take FCAP of its children
-            const int b0 = uni(__shfl(s0, 0, 64));
+            // the first source alone overflows the buffer: take FCAP of its
+            // children (the loaded entries stay those of position t)
+            const int f0 = uni(__shfl(b0, 0, 64));
             for (int f = lane; f < FCAP; f += 64) {
-                F[f] = nodes[b0 + f];
-                FI[f] = b0 + f;
+                F[f] = nodes[f0 + f];
+                FI[f] = f0 + f;
             }
             nF = FCAP;
             skip += FCAP;
@@ -200,13 +206,14 @@ __device__ __forceinline__ void for_source_batches(bool staged, const uint64_t *
             // loads are independent instead of one chain per source)
             if (lane < ntake) {
                 const int off = incl - c;
-                for (int q = 0; q < c; ++q) FI[off + q] = s0 + q;
+                for (int q = 0; q < c; ++q) FI[off + q] = b0 + q;
             }
             nF = uni(__shfl(incl, ntake - 1, 64));
             wave_lds_sync();
             for (int f = lane; f < nF; f += 64) F[f] = nodes[FI[f]];
             t += ntake;
             skip = 0;
+            load(t);
         }
         wave_lds_sync();
         fn(nF);
