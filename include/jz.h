@@ -79,6 +79,10 @@ typedef struct jz_build_opts {
     int auto_regrow;       /* 1 (default): on list overflow grow and rerun; 0: use exactly
                               list_per_node and return JZ_E_CAPACITY on overflow. */
     int keep_keys;         /* 1: keep the sorted Morton keys for jz_tree_export. Default 0. */
+    int sort_max;          /* kNN: longest interaction list put in r_low order before it is
+                              walked (so the walk can stop at the first entry beyond its
+                              radius); longer lists are read unordered. Default 8192, range
+                              [256, 8192]. */
 } jz_build_opts;
 
 /* Fill *o with the defaults above. */
@@ -236,8 +240,9 @@ typedef struct jz_stats {
     int64_t insert_rounds;           /* kNN leaf stage: wave-level top-k insert rounds */
     int64_t tile_steps;              /* kNN leaf stage: wave-level candidate steps */
     int64_t lists_sorted_long;       /* kNN leaf stage: lists longer than the 256 entries staged in
-                                        LDS, sorted through the wave's scratch (<= 1024 entries) */
-    int64_t lists_unordered;         /* kNN leaf stage: lists longer than that, read unordered */
+                                        LDS, put in r_low order (in the wave's LDS scratch up to
+                                        1024 entries, beforehand in HBM up to sort_max) */
+    int64_t lists_unordered;         /* kNN leaf stage: lists longer than sort_max, read unordered */
 } jz_stats;
 
 /* Statistics of the tree and of its last kNN / FoF call. */

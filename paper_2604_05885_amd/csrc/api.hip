@@ -208,6 +208,8 @@ jz_status check_opts(const jz_build_opts &o) {
     if (o.key_bits < 1 || o.key_bits > 21) return jz_fail(JZ_E_INVALID, "key_bits must be in [1, 21]");
     if (!(o.list_per_node >= 1.0f) || !std::isfinite(o.list_per_node))
         return jz_fail(JZ_E_INVALID, "list_per_node must be finite and >= 1");
+    if (o.sort_max < 256 || o.sort_max > 8192)
+        return jz_fail(JZ_E_INVALID, "sort_max must be in [256, 8192]");
     return JZ_OK;
 }
 
@@ -281,6 +283,7 @@ void jz_default_opts(jz_build_opts *o) {
     o->list_per_node = 96.0f;
     o->auto_regrow = 1;
     o->keep_keys = 0;
+    o->sort_max = 8192;
 }
 
 jz_status jz_build(const float *points, int64_t n, void *stream, const jz_build_opts *opts,

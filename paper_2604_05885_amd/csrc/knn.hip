@@ -67,12 +67,19 @@ __device__ void stage_sorted(const int2 *__restrict__ src, int len, uint64_t *L)
 // and written back whole, in order, over its segment in HBM (the segment
 // belongs to this receiver alone); its first LCAP entries stay in L. The
 // segment stays a permutation of the list, so a level that is run again
-// after a capacity overflow reads the same list. Either way the list then
-// reads in r_low order and the walk can stop at the first entry beyond its
-// radius. Returns false (list left as it is, read unordered) when the list
-// exceeds scap.
-__device__ bool stage_list(int2 *__restrict__ gl, int len, uint64_t *S, int scap) {
-    if (len > scap) return false;
+// after a capacity overflow reads the same list. A list of at most
+// presorted entries was already put in order in HBM (k_sort_long): only its
+// first LCAP entries are staged. Either way the list then reads in r_low
+// order and the walk can stop at the first entry beyond its radius. Returns
+// false (list left as it is, read unordered) for a longer list.
+__device__ bool stage_list(int2 *__restrict__ gl, int len, uint64_t *S, int scap,
+                           int presorted) {
+    if (len > scap) {
+        if (len > presorted) return false;
+        for (int i = lane_id(); i < LCAP; i += 64) S[i] = list_key(gl[i]);
+        wave_lds_sync();
+        return true;
+    }
     stage_sorted(gl, len, S);
     if (len > LCAP) {
         for (int i = lane_id(); i < len; i += 64) {
@@ -89,6 +96,68 @@ __device__ bool stage_list(int2 *__restrict__ gl, int len, uint64_t *S, int scap
     }
     wave_lds_sync();
     return true;
+}
+
+// Lists longer than a wave can sort in its LDS scratch are put in order in
+// HBM before they are walked: k_find_long collects the receivers whose list
+// length lies in (min_len, max_len], k_sort_long sorts each such list in
+// place, one workgroup per list, in SORT_MAX keys of LDS.
+constexpr int SORT_MAX = 8192;
+constexpr int SORT_THREADS = 256;
+constexpr int SORT_GRID = 512;  // persistent workgroups (two fit a CU's LDS)
+
+__global__ __launch_bounds__(64) void k_find_long(const int2 *__restrict__ seg, int n,
+                                                  int min_len, int max_len,
+                                                  int *__restrict__ ids,
+                                                  unsigned long long *__restrict__ count) {
+    const int lane = lane_id();
+    const int i = blockIdx.x * 64 + lane;
+    const int len = i < n ? seg[i].y : 0;
+    const bool lng = len > min_len && len <= max_len;
+    const uint64_t m = __ballot(lng);
+    if (m == 0) return;
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(count, (unsigned long long)__popcll(m));
+    base = uni((unsigned long long)__shfl(base, 0, 64));
+    if (lng) ids[base + __popcll(m & lanemask_lt())] = i;
+}
+
+__global__ __launch_bounds__(SORT_THREADS) void k_sort_long(int2 *__restrict__ list,
+                                                            const int2 *__restrict__ seg,
+                                                            const int *__restrict__ ids,
+                                                            const unsigned long long *__restrict__ count) {
+    __shared__ uint64_t s[SORT_MAX];
+    const int tid = threadIdx.x;
+    const long long nl = (long long)*count;
+    for (long long j = blockIdx.x; j < nl; j += gridDim.x) {
+        const int2 sg = seg[ids[j]];
+        int2 *g = list + sg.x;
+        const int len = sg.y;
+        int M = 1;
+        while (M < len) M <<= 1;
+        for (int i = tid; i < M; i += SORT_THREADS) s[i] = i < len ? list_key(g[i]) : ~0ull;
+        __syncthreads();
+        for (int k = 2; k <= M; k <<= 1) {
+            for (int jj = k >> 1; jj > 0; jj >>= 1) {
+                for (int i = tid; i < (M >> 1); i += SORT_THREADS) {
+                    const int a = ((i & ~(jj - 1)) << 1) | (i & (jj - 1));
+                    const int b = a + jj;
+                    const uint64_t x = s[a], y = s[b];
+                    const bool up = (a & k) == 0;
+                    if ((x > y) == up) {
+                        s[a] = y;
+                        s[b] = x;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (int i = tid; i < len; i += SORT_THREADS) {
+            const uint64_t e = s[i];
+            g[i] = make_int2((int)(uint32_t)e, (int)(uint32_t)(e >> 32));
+        }
+        __syncthreads();
+    }
 }
 
 // Entry t of a receiver's list: from LDS for the first LCAP entries of an
@@ -236,7 +305,7 @@ __global__ __launch_bounds__(64 * WPB) void k_knn_step(
     const int *__restrict__ par_spl, const Node *__restrict__ nodes, int n_par, int k,
     int2 *__restrict__ seg_out, int2 *__restrict__ list_out,
     unsigned long long *__restrict__ ctr, long long cap, unsigned long long *overflow,
-    bool sort_long) {
+    int sort_cap, int presorted) {
     // one block per wave: the staged list (LCAP entries), then the staged
     // source children (FCAP records and their indices); before the walk the
     // whole block is the scratch in which a longer list is sorted
@@ -252,7 +321,7 @@ __global__ __launch_bounds__(64 * WPB) void k_knn_step(
     uint64_t *L = s_raw[w];
     Node *F = reinterpret_cast<Node *>(L + LCAP);
     int *FI = reinterpret_cast<int *>(L + LCAP + FCAP * (int)(sizeof(Node) / 8));
-    const bool staged = stage_list(gl, len, L, sort_long ? prev_pow2(RAW) : LCAP);
+    const bool staged = stage_list(gl, len, L, min(sort_cap, prev_pow2(RAW)), presorted);
 
     for (int cb = c0; cb < c1; cb += 64) {
         const int nc = min(64, c1 - cb);
@@ -546,7 +615,8 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
     const int2 *__restrict__ seg, int2 *__restrict__ list, const Node *__restrict__ leaves,
     const float4 *__restrict__ pts, int n_leaves, const int *__restrict__ leaf_base,
     int32_t *__restrict__ out_idx, float *__restrict__ out_d2,
-    unsigned long long *__restrict__ stats, const unsigned long long *__restrict__ overflow) {
+    unsigned long long *__restrict__ stats, const unsigned long long *__restrict__ overflow,
+    int sort_cap, int presorted) {
     // one block per wave: the staged list (LCAP entries), the point tile,
     // the (lo, hi) box of every 8 tile positions and the candidate queues;
     // before the walk the whole block is the scratch in which a longer list
@@ -575,7 +645,7 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
     float4 *cbox = reinterpret_cast<float4 *>(L + O_BOX);
     Node *nb = s_nodes[w];
     int *offs = s_offs[w];
-    const bool staged = stage_list(gl, len, L, prev_pow2(RAW));
+    const bool staged = stage_list(gl, len, L, min(sort_cap, prev_pow2(RAW)), presorted);
 
     const double pad = __builtin_bit_cast(double, PAD_KEY);
     TopK<K> best;
@@ -832,7 +902,8 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
 }
 
 typedef void (*leaf_fn)(const int2 *, int2 *, const Node *, const float4 *, int, const int *,
-                        int32_t *, float *, unsigned long long *, const unsigned long long *);
+                        int32_t *, float *, unsigned long long *, const unsigned long long *, int,
+                        int);
 
 template <int K>
 leaf_fn leaf_ptr() {
@@ -867,8 +938,10 @@ jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s) 
 
     // counters: four leaf statistics (evaluations, sources visited, insert
     // rounds, tile steps)
+    // then one counter of long lists per walk level and one for the leaf stage
     DBuf d_ctr;
-    const size_t nctr = ctr_words(6);
+    const size_t c_long = ctr_words(6);
+    const size_t nctr = c_long + JZ_MAX_PLANES + 1;
     JZ_TRY(d_ctr.get(ac, nctr * sizeof(unsigned long long), s));
     unsigned long long *ctr = d_ctr.as<unsigned long long>();
     JZ_HIP(hipMemsetAsync(ctr, 0, d_ctr.bytes, s));
@@ -878,6 +951,19 @@ jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s) 
         cap[p] = initial_cap(t, CAP_KNN, k, p);
         JZ_TRY(segs[p].get(ac, t->L[p] * sizeof(int2), s));
     }
+    // Lists longer than a wave sorts in LDS (512 entries in the walk, 1024 in
+    // the leaf stage), up to sort_max, are sorted in HBM before their level.
+    const int sort_max = t->opts.sort_max;
+    const int walk_cap = std::min(sort_max, 512), leaf_cap = std::min(sort_max, 1024);
+    DBuf d_ids;
+    JZ_TRY(d_ids.get(ac, (size_t)t->L[0] * sizeof(int), s));
+    auto presort = [&](int2 *list, const int2 *seg, int64_t n, int min_len,
+                       unsigned long long *count) {
+        if (sort_max <= min_len) return;
+        k_find_long<<<(unsigned)((n + 63) / 64), 64, 0, s>>>(seg, (int)n, min_len, sort_max,
+                                                             d_ids.as<int>(), count);
+        k_sort_long<<<SORT_GRID, SORT_THREADS, 0, s>>>(list, seg, d_ids.as<int>(), count);
+    };
     EventSet ev(jz_profiling());
 
     // Level p turns the list of plane p+1 (or of the super nodes) into the
@@ -895,19 +981,23 @@ jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s) 
             int2 *list_in = top ? t->knn_top_list.as<int2>() : lists[p + 1].as<int2>();
             const int *par_spl = top ? t->super_spl.as<int>() : t->spl[p + 1].as<int>();
             const int64_t n_par = top ? t->S : t->L[p + 1];
+            if (!top) presort(list_in, seg_in, n_par, walk_cap, ctr + c_long + p);
             k_knn_step<<<blocks_for(n_par, WPB), 64 * WPB, 0, s>>>(seg_in, list_in, par_spl,
                                                             t->nodes[p].as<Node>(), (int)n_par, k,
                                                             segs[p].as<int2>(), lists[p].as<int2>(),
                                                             ctr + (size_t)p * LIST_ARENAS,
                                                             cap[p] / LIST_ARENAS, ctr + CTR_FLAG,
-                                                            !top);
+                                                            top ? LCAP : walk_cap,
+                                                            top ? 0 : sort_max);
         }
+        presort(lists[0].as<int2>(), segs[0].as<int2>(), t->L[0], leaf_cap,
+                ctr + c_long + JZ_MAX_PLANES);
         JZ_HIP(hipGetLastError());
         if (ev.on) JZ_HIP(hipEventRecord(ev[1], s));
         leaf_kernel(k)<<<blocks_for(t->L[0], WPB), 64 * WPB, 0, s>>>(
             segs[0].as<int2>(), lists[0].as<int2>(), t->nodes[0].as<Node>(), t->pts4.as<float4>(),
             (int)t->L[0], t->nsets > 1 ? t->leaf_base.as<int>() : nullptr, idx, dist2,
-            ctr + CTR_STATS, ctr + CTR_FLAG);
+            ctr + CTR_STATS, ctr + CTR_FLAG, leaf_cap, sort_max);
         JZ_HIP(hipGetLastError());
         if (ev.on) JZ_HIP(hipEventRecord(ev[2], s));
         std::vector<unsigned long long> hc(nctr);

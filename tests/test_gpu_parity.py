@@ -92,15 +92,19 @@ def test_knn_tree_shapes(jz, leaf_max, k):
 
 def test_knn_long_lists(jz):
     """Leaves of at most 8 points in dense clumps with k = 32: many leaf lists
-    are longer than the 256 entries staged in LDS. Those of at most 1024 are
-    sorted through the wave's scratch and partly read back from HBM, longer
-    ones are read unordered; both kinds must occur, and the whole result must
-    equal the exact kd-tree oracle."""
+    are longer than the 256 entries staged in LDS, some longer than the 1024
+    a wave sorts in its LDS scratch. With the default sort_max every list is
+    put in order (in LDS, or in HBM before its level); with sort_max = 512
+    the longer ones are read unordered. Both must equal the exact kd-tree
+    oracle."""
     p = inputs.clustered(60000, 16, 21)
-    gi, gd, st = gpu_knn(jz, p, 32, leaf_max=8)
-    assert st["lists_sorted_long"] > 0 and st["lists_unordered"] > 0, st
     wi, wd = oracle.knn_kd(p, 32)
+    gi, gd, st = gpu_knn(jz, p, 32, leaf_max=8)
+    assert st["lists_sorted_long"] > 0 and st["lists_unordered"] == 0, st
     assert_knn_equal(gi, gd, wi, wd, "long lists")
+    gi, gd, st = gpu_knn(jz, p, 32, leaf_max=8, sort_max=512)
+    assert st["lists_sorted_long"] > 0 and st["lists_unordered"] > 0, st
+    assert_knn_equal(gi, gd, wi, wd, "long lists, sort_max=512")
     # the same with list capacities far too small: levels are run again and
     # read lists that their first attempt already sorted in place (k = 31,
     # used by no other test, so no learned capacity applies; its exact
