@@ -290,8 +290,33 @@ __device__ __forceinline__ void for_source_batches(bool staged, const uint64_t *
     }
 }
 
-// Level step of the kNN walk: one wave per receiving parent. Its children are
-// spread over the lanes with G = 64 / (children, rounded up to a power of 2)
+// The walk's work items: a receiving parent with more than WALK_CB children
+// is split into items of WALK_CB children (each a wave of its own, reading
+// the parent's list), so that the few parents with many children and long
+// lists do not leave one wave running long after the rest of the level.
+constexpr int WALK_CB = 8;
+
+__global__ __launch_bounds__(64) void k_walk_items(const int *__restrict__ par_spl, int n_par,
+                                                   int2 *__restrict__ items,
+                                                   unsigned long long *__restrict__ count) {
+    const int lane = lane_id();
+    const int P = blockIdx.x * 64 + lane;
+    int c0 = 0, nb = 0;
+    if (P < n_par) {
+        c0 = par_spl[P];
+        nb = max(1, (par_spl[P + 1] - c0 + WALK_CB - 1) / WALK_CB);
+    }
+    const int incl = wave_incl_scan(nb);
+    const int tot = uni(__shfl(incl, 63, 64));
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(count, (unsigned long long)tot);
+    base = uni((unsigned long long)__shfl(base, 0, 64));
+    for (int b = 0; b < nb; ++b)
+        items[base + (unsigned long long)(incl - nb + b)] = make_int2(P, c0 + b * WALK_CB);
+}
+
+// Level step of the kNN walk: one wave per work item (a receiving parent and
+// up to WALK_CB of its children). The children are spread over the lanes with G = 64 / (children, rounded up to a power of 2)
 // lanes per child; the G lanes of a child split the staged source children
 // between them (slice sl takes f = sl, sl + G, ...).
 //   pass 1  FindRmax: a register heap of (d_up^2, count) per lane; the G
@@ -301,8 +326,9 @@ __device__ __forceinline__ void for_source_batches(bool staged, const uint64_t *
 //   pass 3  insert them (with r_low = d_low^2) at offsets reserved with one
 //           atomic per wave; a child's entries are contiguous.
 __global__ __launch_bounds__(64 * WPB) void k_knn_step(
+    const int2 *__restrict__ items, const unsigned long long *__restrict__ n_items,
     const int2 *__restrict__ seg_in, int2 *__restrict__ list_in,
-    const int *__restrict__ par_spl, const Node *__restrict__ nodes, int n_par, int k,
+    const int *__restrict__ par_spl, const Node *__restrict__ nodes, int k,
     int2 *__restrict__ seg_out, int2 *__restrict__ list_out,
     unsigned long long *__restrict__ ctr, long long cap, unsigned long long *overflow,
     int sort_cap, int presorted) {
@@ -312,12 +338,16 @@ __global__ __launch_bounds__(64 * WPB) void k_knn_step(
     constexpr int RAW = LCAP + FCAP * (int)(sizeof(Node) / 8) + FCAP / 2;
     __shared__ __align__(16) uint64_t s_raw[WPB][RAW];
     const int w = WPB == 1 ? 0 : uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
-    const int P = xcd_block(blockIdx.x, gridDim.x) * WPB + w;
-    if (P >= n_par) return;
+    // work item I: receiving parent it.x, its children from it.y (at most
+    // WALK_CB of them)
+    const int I = xcd_block(blockIdx.x, gridDim.x) * WPB + w;
+    if (I >= (int)uni(*n_items)) return;
+    const int2 it = items[I];
+    const int P = uni(it.x);
     const int2 sg = seg_in[P];
     int2 *gl = list_in + uni(sg.x);
     const int len = uni(sg.y);
-    const int c0 = uni(par_spl[P]), c1 = uni(par_spl[P + 1]);
+    const int c0 = uni(it.y), c1 = uni(min(par_spl[P + 1], it.y + WALK_CB));
     uint64_t *L = s_raw[w];
     Node *F = reinterpret_cast<Node *>(L + LCAP);
     int *FI = reinterpret_cast<int *>(L + LCAP + FCAP * (int)(sizeof(Node) / 8));
@@ -396,8 +426,8 @@ __global__ __launch_bounds__(64 * WPB) void k_knn_step(
         // reserve: lanes are child-major, so a wave scan gives contiguous segments
         const int incl = wave_incl_scan(cnt);
         const int total = uni(__shfl(incl, 63, 64));
-        // segment in arena P % LIST_ARENAS (cap entries each)
-        const int ar = P & (LIST_ARENAS - 1);
+        // segment in arena I % LIST_ARENAS (cap entries each)
+        const int ar = I & (LIST_ARENAS - 1);
         unsigned long long lb = 0;
         if (lane == 0) lb = atomicAdd(ctr + ar, (unsigned long long)total);
         lb = uni((unsigned long long)__shfl(lb, 0, 64));
@@ -938,10 +968,11 @@ jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s) 
 
     // counters: four leaf statistics (evaluations, sources visited, insert
     // rounds, tile steps)
-    // then one counter of long lists per walk level and one for the leaf stage
+    // then one counter of long lists per walk level and one for the leaf
+    // stage, and one counter of work items per walk level
     DBuf d_ctr;
-    const size_t c_long = ctr_words(6);
-    const size_t nctr = c_long + JZ_MAX_PLANES + 1;
+    const size_t c_long = ctr_words(6), c_items = c_long + JZ_MAX_PLANES + 1;
+    const size_t nctr = c_items + JZ_MAX_PLANES;
     JZ_TRY(d_ctr.get(ac, nctr * sizeof(unsigned long long), s));
     unsigned long long *ctr = d_ctr.as<unsigned long long>();
     JZ_HIP(hipMemsetAsync(ctr, 0, d_ctr.bytes, s));
@@ -951,10 +982,21 @@ jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s) 
         cap[p] = initial_cap(t, CAP_KNN, k, p);
         JZ_TRY(segs[p].get(ac, t->L[p] * sizeof(int2), s));
     }
-    // Lists longer than a wave sorts in LDS (512 entries in the walk, 1024 in
-    // the leaf stage), up to sort_max, are sorted in HBM before their level.
+    // Lists longer than a wave sorts in LDS (LCAP entries in the walk, whose
+    // items of one parent share its list, 1024 in the leaf stage), up to
+    // sort_max, are sorted in HBM before their level.
     const int sort_max = t->opts.sort_max;
-    const int walk_cap = std::min(sort_max, 512), leaf_cap = std::min(sort_max, 1024);
+    const int walk_cap = LCAP, leaf_cap = std::min(sort_max, 1024);
+    // work items of the walk (at most one per parent plus one per WALK_CB
+    // children)
+    auto item_bound = [&](int p) {
+        const int64_t n_par = p == P - 1 ? t->S : t->L[p + 1];
+        return n_par + t->L[p] / WALK_CB + 1;
+    };
+    int64_t max_items = 0;
+    for (int p = 0; p < P; ++p) max_items = std::max(max_items, item_bound(p));
+    DBuf d_items;
+    JZ_TRY(d_items.get(ac, (size_t)max_items * sizeof(int2), s));
     DBuf d_ids;
     JZ_TRY(d_ids.get(ac, (size_t)t->L[0] * sizeof(int), s));
     auto presort = [&](int2 *list, const int2 *seg, int64_t n, int min_len,
@@ -982,8 +1024,11 @@ jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s) 
             const int *par_spl = top ? t->super_spl.as<int>() : t->spl[p + 1].as<int>();
             const int64_t n_par = top ? t->S : t->L[p + 1];
             if (!top) presort(list_in, seg_in, n_par, walk_cap, ctr + c_long + p);
-            k_knn_step<<<blocks_for(n_par, WPB), 64 * WPB, 0, s>>>(seg_in, list_in, par_spl,
-                                                            t->nodes[p].as<Node>(), (int)n_par, k,
+            unsigned long long *n_items = ctr + c_items + p;
+            k_walk_items<<<(unsigned)((n_par + 63) / 64), 64, 0, s>>>(par_spl, (int)n_par,
+                                                                     d_items.as<int2>(), n_items);
+            k_knn_step<<<blocks_for(item_bound(p), WPB), 64 * WPB, 0, s>>>(
+                d_items.as<int2>(), n_items, seg_in, list_in, par_spl, t->nodes[p].as<Node>(), k,
                                                             segs[p].as<int2>(), lists[p].as<int2>(),
                                                             ctr + (size_t)p * LIST_ARENAS,
                                                             cap[p] / LIST_ARENAS, ctr + CTR_FLAG,
