@@ -68,7 +68,7 @@ __device__ void stage_sorted(const int2 *__restrict__ src, int len, uint64_t *L)
 // belongs to this receiver alone); its first LCAP entries stay in L. The
 // segment stays a permutation of the list, so a level that is run again
 // after a capacity overflow reads the same list. A list of at most
-// presorted entries was already put in order in HBM (k_sort_long): only its
+// presorted entries was already put in order in HBM (k_sort_lists): only its
 // first LCAP entries are staged. Either way the list then reads in r_low
 // order and the walk can stop at the first entry beyond its radius. Returns
 // false (list left as it is, read unordered) for a longer list.
@@ -100,48 +100,73 @@ __device__ bool stage_list(int2 *__restrict__ gl, int len, uint64_t *S, int scap
 
 // Lists longer than a wave can sort in its LDS scratch are put in order in
 // HBM before they are walked: k_find_long collects the receivers whose list
-// length lies in (min_len, max_len], k_sort_long sorts each such list in
-// place, one workgroup per list, in SORT_MAX keys of LDS.
+// length lies in (min_len, mid] and in (mid, max_len], and k_sort_lists
+// sorts each such list in place in LDS, one workgroup per list: one wave for
+// lists of at most SORT_MID entries, SORT_WAVES waves for longer ones (up to
+// SORT_MAX).
+constexpr int SORT_MID = 1024;
 constexpr int SORT_MAX = 8192;
-constexpr int SORT_THREADS = 256;
-constexpr int SORT_GRID = 512;  // persistent workgroups (two fit a CU's LDS)
+constexpr int SORT_WAVES = 4;
 
 __global__ __launch_bounds__(64) void k_find_long(const int2 *__restrict__ seg, int n,
-                                                  int min_len, int max_len,
-                                                  int *__restrict__ ids,
-                                                  unsigned long long *__restrict__ count) {
+                                                  int min_len, int mid, int max_len,
+                                                  int *__restrict__ ids_a,
+                                                  unsigned long long *__restrict__ count_a,
+                                                  int *__restrict__ ids_b,
+                                                  unsigned long long *__restrict__ count_b) {
     const int lane = lane_id();
     const int i = blockIdx.x * 64 + lane;
     const int len = i < n ? seg[i].y : 0;
-    const bool lng = len > min_len && len <= max_len;
-    const uint64_t m = __ballot(lng);
-    if (m == 0) return;
-    unsigned long long base = 0;
-    if (lane == 0) base = atomicAdd(count, (unsigned long long)__popcll(m));
-    base = uni((unsigned long long)__shfl(base, 0, 64));
-    if (lng) ids[base + __popcll(m & lanemask_lt())] = i;
+    const bool la = len > min_len && len <= mid, lb = len > mid && len <= max_len;
+    const uint64_t ma = __ballot(la), mb = __ballot(lb);
+    if (ma) {
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(count_a, (unsigned long long)__popcll(ma));
+        base = uni((unsigned long long)__shfl(base, 0, 64));
+        if (la) ids_a[base + __popcll(ma & lanemask_lt())] = i;
+    }
+    if (mb) {
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(count_b, (unsigned long long)__popcll(mb));
+        base = uni((unsigned long long)__shfl(base, 0, 64));
+        if (lb) ids_b[base + __popcll(mb & lanemask_lt())] = i;
+    }
 }
 
-__global__ __launch_bounds__(SORT_THREADS) void k_sort_long(int2 *__restrict__ list,
-                                                            const int2 *__restrict__ seg,
-                                                            const int *__restrict__ ids,
-                                                            const unsigned long long *__restrict__ count) {
-    __shared__ uint64_t s[SORT_MAX];
-    const int tid = threadIdx.x;
+// Bitonic sort of each listed segment by (r_low, source), in CAP keys of LDS,
+// by NW waves. A compare-exchange step of pair distance j touches, for pair
+// indices in one aligned range of PW = M / 2 / NW pairs, only the elements of
+// one aligned range of 2 PW: steps with j <= PW run wave by wave without a
+// workgroup barrier, so only the few steps of larger j pay one.
+template <int CAP, int NW>
+__global__ __launch_bounds__(64 * NW) void k_sort_lists(int2 *__restrict__ list,
+                                                        const int2 *__restrict__ seg,
+                                                        const int *__restrict__ ids,
+                                                        const unsigned long long *__restrict__ count) {
+    __shared__ uint64_t s[CAP];
+    constexpr int NT = 64 * NW;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const long long nl = (long long)*count;
-    for (long long j = blockIdx.x; j < nl; j += gridDim.x) {
-        const int2 sg = seg[ids[j]];
+    for (long long jl = blockIdx.x; jl < nl; jl += gridDim.x) {
+        const int2 sg = seg[ids[jl]];
         int2 *g = list + sg.x;
         const int len = sg.y;
-        int M = 1;
+        int M = 2 * NW;
         while (M < len) M <<= 1;
-        for (int i = tid; i < M; i += SORT_THREADS) s[i] = i < len ? list_key(g[i]) : ~0ull;
+        for (int i = tid; i < M; i += NT) s[i] = i < len ? list_key(g[i]) : ~0ull;
         __syncthreads();
+        const int PW = (M >> 1) / NW;
         for (int k = 2; k <= M; k <<= 1) {
-            for (int jj = k >> 1; jj > 0; jj >>= 1) {
-                for (int i = tid; i < (M >> 1); i += SORT_THREADS) {
-                    const int a = ((i & ~(jj - 1)) << 1) | (i & (jj - 1));
-                    const int b = a + jj;
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                const bool wide = j > PW;
+                // a wide step reads what other waves wrote in the steps before
+                if (wide) __syncthreads();
+                const int i0 = wide ? tid : w * PW + lane;
+                const int i1 = wide ? (M >> 1) : (w + 1) * PW;
+                const int di = wide ? NT : 64;
+                for (int i = i0; i < i1; i += di) {
+                    const int a = ((i & ~(j - 1)) << 1) | (i & (j - 1));
+                    const int b = a + j;
                     const uint64_t x = s[a], y = s[b];
                     const bool up = (a & k) == 0;
                     if ((x > y) == up) {
@@ -149,10 +174,12 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_long(int2 *__restrict__ l
                         s[b] = x;
                     }
                 }
-                __syncthreads();
+                if (wide || NW == 1) __syncthreads();
+                else wave_lds_sync();
             }
         }
-        for (int i = tid; i < len; i += SORT_THREADS) {
+        __syncthreads();
+        for (int i = tid; i < len; i += NT) {
             const uint64_t e = s[i];
             g[i] = make_int2((int)(uint32_t)e, (int)(uint32_t)(e >> 32));
         }
@@ -968,10 +995,11 @@ jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s) 
 
     // counters: four leaf statistics (evaluations, sources visited, insert
     // rounds, tile steps)
-    // then one counter of long lists per walk level and one for the leaf
-    // stage, and one counter of work items per walk level
+    // then two counters of long lists (up to SORT_MID entries, longer) per
+    // walk level and for the leaf stage, and one counter of work items per
+    // walk level
     DBuf d_ctr;
-    const size_t c_long = ctr_words(6), c_items = c_long + JZ_MAX_PLANES + 1;
+    const size_t c_long = ctr_words(6), c_items = c_long + 2 * (JZ_MAX_PLANES + 1);
     const size_t nctr = c_items + JZ_MAX_PLANES;
     JZ_TRY(d_ctr.get(ac, nctr * sizeof(unsigned long long), s));
     unsigned long long *ctr = d_ctr.as<unsigned long long>();
@@ -998,13 +1026,19 @@ jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s) 
     DBuf d_items;
     JZ_TRY(d_items.get(ac, (size_t)max_items * sizeof(int2), s));
     DBuf d_ids;
-    JZ_TRY(d_ids.get(ac, (size_t)t->L[0] * sizeof(int), s));
+    JZ_TRY(d_ids.get(ac, 2 * (size_t)t->L[0] * sizeof(int), s));
     auto presort = [&](int2 *list, const int2 *seg, int64_t n, int min_len,
                        unsigned long long *count) {
         if (sort_max <= min_len) return;
-        k_find_long<<<(unsigned)((n + 63) / 64), 64, 0, s>>>(seg, (int)n, min_len, sort_max,
-                                                             d_ids.as<int>(), count);
-        k_sort_long<<<SORT_GRID, SORT_THREADS, 0, s>>>(list, seg, d_ids.as<int>(), count);
+        int *ids_a = d_ids.as<int>(), *ids_b = ids_a + t->L[0];
+        const int mid = std::max(min_len, std::min(sort_max, SORT_MID));
+        k_find_long<<<(unsigned)((n + 63) / 64), 64, 0, s>>>(seg, (int)n, min_len, mid, sort_max,
+                                                             ids_a, count, ids_b, count + 1);
+        if (mid > min_len)
+            k_sort_lists<SORT_MID, 1><<<4096, 64, 0, s>>>(list, seg, ids_a, count);
+        if (sort_max > mid)
+            k_sort_lists<SORT_MAX, SORT_WAVES><<<512, 64 * SORT_WAVES, 0, s>>>(list, seg, ids_b,
+                                                                              count + 1);
     };
     EventSet ev(jz_profiling());
 
@@ -1023,7 +1057,7 @@ jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s) 
             int2 *list_in = top ? t->knn_top_list.as<int2>() : lists[p + 1].as<int2>();
             const int *par_spl = top ? t->super_spl.as<int>() : t->spl[p + 1].as<int>();
             const int64_t n_par = top ? t->S : t->L[p + 1];
-            if (!top) presort(list_in, seg_in, n_par, walk_cap, ctr + c_long + p);
+            if (!top) presort(list_in, seg_in, n_par, walk_cap, ctr + c_long + 2 * p);
             unsigned long long *n_items = ctr + c_items + p;
             k_walk_items<<<(unsigned)((n_par + 63) / 64), 64, 0, s>>>(par_spl, (int)n_par,
                                                                      d_items.as<int2>(), n_items);
@@ -1036,7 +1070,7 @@ jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s) 
                                                             top ? 0 : sort_max);
         }
         presort(lists[0].as<int2>(), segs[0].as<int2>(), t->L[0], leaf_cap,
-                ctr + c_long + JZ_MAX_PLANES);
+                ctr + c_long + 2 * JZ_MAX_PLANES);
         JZ_HIP(hipGetLastError());
         if (ev.on) JZ_HIP(hipEventRecord(ev[1], s));
         leaf_kernel(k)<<<blocks_for(t->L[0], WPB), 64 * WPB, 0, s>>>(
