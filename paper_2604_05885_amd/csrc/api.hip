@@ -102,12 +102,23 @@ size_t round_size(size_t b) {
     return r;
 }
 
+// Wait for the work a free block's event marks and destroy the event. An
+// event whose wait fails (for instance one last recorded on a stream that no
+// longer exists) is replaced by a wait for the whole device, and the error is
+// cleared so that it cannot surface in an unrelated later check.
+void retire_event(hipEvent_t ev) {
+    if (!ev) return;
+    if (hipEventSynchronize(ev) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipDeviceSynchronize();
+        (void)hipGetLastError();
+    }
+    if (hipEventDestroy(ev) != hipSuccess) (void)hipGetLastError();
+}
+
 void release_all(Pool &P) {
     for (auto &kv : P.free) {
-        if (kv.second.ev) {
-            (void)hipEventSynchronize(kv.second.ev);
-            (void)hipEventDestroy(kv.second.ev);
-        }
+        retire_event(kv.second.ev);
         (void)hipFree(kv.second.p);
     }
     P.free.clear();
@@ -132,8 +143,11 @@ void *dev_alloc(const AllocCtx &a, size_t bytes, hipStream_t s) {
     }
     if (found) {
         if (blk.ev) {
-            if (blk.s != s) (void)hipEventSynchronize(blk.ev);
-            (void)hipEventDestroy(blk.ev);
+            if (blk.s != s) {
+                retire_event(blk.ev);
+            } else if (hipEventDestroy(blk.ev) != hipSuccess) {
+                (void)hipGetLastError();
+            }
         }
         std::lock_guard<std::mutex> lk(P.m);
         P.live[blk.p] = blk.bytes;
@@ -179,6 +193,17 @@ void dev_free(const AllocCtx &a, void *p, size_t bytes, hipStream_t s) {
     const size_t real = it != P.live.end() ? it->second : round_size(bytes);
     if (it != P.live.end()) P.live.erase(it);
     P.free.emplace(real, Block{p, real, s, ev});
+}
+
+void pool_forget_stream(int device, hipStream_t s) {
+    Pool &P = pool(device);
+    std::lock_guard<std::mutex> lk(P.m);
+    for (auto &kv : P.free) {
+        if (kv.second.s != s) continue;
+        retire_event(kv.second.ev);
+        kv.second.ev = nullptr;
+        kv.second.s = nullptr;
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -41,6 +41,10 @@ struct AllocCtx {
 
 void *dev_alloc(const AllocCtx &a, size_t bytes, hipStream_t s);
 void dev_free(const AllocCtx &a, void *p, size_t bytes, hipStream_t s);
+// Before a stream is destroyed: wait for the cached blocks last used on it
+// and drop their events (an event last recorded on a destroyed stream must
+// not be waited on).
+void pool_forget_stream(int device, hipStream_t s);
 
 // A device buffer owned by a tree or by one call.
 struct DBuf {

@@ -234,7 +234,12 @@ void worker(jz_server *S) {
         S->cv_work.notify_all();
     }
     lk.unlock();
-    if (stream) (void)hipStreamDestroy(stream);
+    if (stream) {
+        (void)hipStreamSynchronize(stream);
+        pool_forget_stream(S->device, stream);
+        (void)hipStreamDestroy(stream);
+        (void)hipGetLastError();
+    }
 }
 
 }  // namespace

@@ -108,3 +108,32 @@ def test_autotune_picks_valid_options(jz):
         wi, wd = oracle.knn_bf(p, 8)
         assert np.array_equal(i.cpu().numpy(), wi) and np.array_equal(dd.cpu().numpy(), wd)
         assert np.array_equal(lab.cpu().numpy(), oracle.fof_bf(p, b))
+
+
+def test_servers_in_sequence_reuse_cached_memory(jz):
+    """Servers created and destroyed one after another: each leaves device
+    blocks in the library's cache that its worker streams used last; the next
+    server's streams, and a plain call on the default stream, take them over
+    after the streams they were used on are gone. Every request must
+    succeed and give the same result."""
+    p = torch.from_numpy(inputs.clustered(200000, 64, 31)).cuda()
+    b = float(inputs.linking_length(200000, 0.2))
+    torch.cuda.synchronize()
+    first = None
+    for rep in range(4):
+        with jz.Server(streams=2, max_batch_sets=2) as S:
+            ts = [S.submit_knn(p, 16), S.submit_fof(p, b), S.submit_knn(p, 16)]
+            outs = [S.wait(t)[0] for t in ts]
+            st = S.stats()
+            assert st["failed"] == 0, (rep, st)
+            got = (outs[0][0].cpu(), outs[1][0].cpu(), outs[2][0].cpu())
+            for t in ts:
+                S.release(t)
+        assert torch.equal(got[0], got[2])
+        if first is None:
+            first = got
+        else:
+            assert all(torch.equal(a, c) for a, c in zip(first, got)), rep
+    with jz.jz_build(p) as t:
+        i, _ = t.knn(16)
+        assert torch.equal(i.cpu(), first[0])
