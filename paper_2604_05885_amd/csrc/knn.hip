@@ -317,21 +317,24 @@ __device__ __forceinline__ void for_source_batches(bool staged, const uint64_t *
     }
 }
 
-// The walk's work items: a receiving parent with more than WALK_CB children
-// is split into items of WALK_CB children (each a wave of its own, reading
-// the parent's list), so that the few parents with many children and long
-// lists do not leave one wave running long after the rest of the level.
+// The walk's work items: a receiving parent with more than cb children is
+// split into items of cb children (each a wave of its own, reading the
+// parent's list), so that the few parents with many children and long lists
+// do not leave one wave running long after the rest of the level, and so
+// that the upper levels, with few parents, still fill the device. cb is at
+// most WALK_CB.
 constexpr int WALK_CB = 8;
+constexpr int WALK_CB_UP = 2;
 
 __global__ __launch_bounds__(64) void k_walk_items(const int *__restrict__ par_spl, int n_par,
-                                                   int2 *__restrict__ items,
+                                                   int cb, int2 *__restrict__ items,
                                                    unsigned long long *__restrict__ count) {
     const int lane = lane_id();
     const int P = blockIdx.x * 64 + lane;
     int c0 = 0, nb = 0;
     if (P < n_par) {
         c0 = par_spl[P];
-        nb = max(1, (par_spl[P + 1] - c0 + WALK_CB - 1) / WALK_CB);
+        nb = max(1, (par_spl[P + 1] - c0 + cb - 1) / cb);
     }
     const int incl = wave_incl_scan(nb);
     const int tot = uni(__shfl(incl, 63, 64));
@@ -339,7 +342,7 @@ __global__ __launch_bounds__(64) void k_walk_items(const int *__restrict__ par_s
     if (lane == 0) base = atomicAdd(count, (unsigned long long)tot);
     base = uni((unsigned long long)__shfl(base, 0, 64));
     for (int b = 0; b < nb; ++b)
-        items[base + (unsigned long long)(incl - nb + b)] = make_int2(P, c0 + b * WALK_CB);
+        items[base + (unsigned long long)(incl - nb + b)] = make_int2(P, c0 + b * cb);
 }
 
 // Level step of the kNN walk: one wave per work item (a receiving parent and
@@ -353,7 +356,7 @@ __global__ __launch_bounds__(64) void k_walk_items(const int *__restrict__ par_s
 //   pass 3  insert them (with r_low = d_low^2) at offsets reserved with one
 //           atomic per wave; a child's entries are contiguous.
 __global__ __launch_bounds__(64 * WPB) void k_knn_step(
-    const int2 *__restrict__ items, const unsigned long long *__restrict__ n_items,
+    const int2 *__restrict__ items, const unsigned long long *__restrict__ n_items, int cb,
     const int2 *__restrict__ seg_in, int2 *__restrict__ list_in,
     const int *__restrict__ par_spl, const Node *__restrict__ nodes, int k,
     int2 *__restrict__ seg_out, int2 *__restrict__ list_out,
@@ -365,8 +368,8 @@ __global__ __launch_bounds__(64 * WPB) void k_knn_step(
     constexpr int RAW = LCAP + FCAP * (int)(sizeof(Node) / 8) + FCAP / 2;
     __shared__ __align__(16) uint64_t s_raw[WPB][RAW];
     const int w = WPB == 1 ? 0 : uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
-    // work item I: receiving parent it.x, its children from it.y (at most
-    // WALK_CB of them)
+    // work item I: receiving parent it.x, its children from it.y (at most cb
+    // of them)
     const int I = xcd_block(blockIdx.x, gridDim.x) * WPB + w;
     if (I >= (int)uni(*n_items)) return;
     const int2 it = items[I];
@@ -374,7 +377,7 @@ __global__ __launch_bounds__(64 * WPB) void k_knn_step(
     const int2 sg = seg_in[P];
     int2 *gl = list_in + uni(sg.x);
     const int len = uni(sg.y);
-    const int c0 = uni(it.y), c1 = uni(min(par_spl[P + 1], it.y + WALK_CB));
+    const int c0 = uni(it.y), c1 = uni(min(par_spl[P + 1], it.y + cb));
     uint64_t *L = s_raw[w];
     Node *F = reinterpret_cast<Node *>(L + LCAP);
     int *FI = reinterpret_cast<int *>(L + LCAP + FCAP * (int)(sizeof(Node) / 8));
@@ -1015,11 +1018,16 @@ jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s) 
     // sort_max, are sorted in HBM before their level.
     const int sort_max = t->opts.sort_max;
     const int walk_cap = LCAP, leaf_cap = std::min(sort_max, 1024);
-    // work items of the walk (at most one per parent plus one per WALK_CB
-    // children)
+    // work items of the walk (at most one per parent plus one per cb
+    // children): WALK_CB children per item at the leaf level, WALK_CB_UP
+    // above it, where there are few parents
+    auto cb_of = [&](int p) {
+        const int64_t n_par = p == P - 1 ? t->S : t->L[p + 1];
+        return p == 0 || n_par >= 4096 ? WALK_CB : WALK_CB_UP;
+    };
     auto item_bound = [&](int p) {
         const int64_t n_par = p == P - 1 ? t->S : t->L[p + 1];
-        return n_par + t->L[p] / WALK_CB + 1;
+        return n_par + t->L[p] / cb_of(p) + 1;
     };
     int64_t max_items = 0;
     for (int p = 0; p < P; ++p) max_items = std::max(max_items, item_bound(p));
@@ -1059,10 +1067,10 @@ jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s) 
             const int64_t n_par = top ? t->S : t->L[p + 1];
             if (!top) presort(list_in, seg_in, n_par, walk_cap, ctr + c_long + 2 * p);
             unsigned long long *n_items = ctr + c_items + p;
-            k_walk_items<<<(unsigned)((n_par + 63) / 64), 64, 0, s>>>(par_spl, (int)n_par,
-                                                                     d_items.as<int2>(), n_items);
+            k_walk_items<<<(unsigned)((n_par + 63) / 64), 64, 0, s>>>(
+                par_spl, (int)n_par, cb_of(p), d_items.as<int2>(), n_items);
             k_knn_step<<<blocks_for(item_bound(p), WPB), 64 * WPB, 0, s>>>(
-                d_items.as<int2>(), n_items, seg_in, list_in, par_spl, t->nodes[p].as<Node>(), k,
+                d_items.as<int2>(), n_items, cb_of(p), seg_in, list_in, par_spl, t->nodes[p].as<Node>(), k,
                                                             segs[p].as<int2>(), lists[p].as<int2>(),
                                                             ctr + (size_t)p * LIST_ARENAS,
                                                             cap[p] / LIST_ARENAS, ctr + CTR_FLAG,
