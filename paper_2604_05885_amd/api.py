@@ -15,6 +15,13 @@ import re
 
 import numpy as np
 
+# torch before libjz.so: both need libamdhip64.so.7, and the dynamic loader
+# binds a later library to the copy already loaded. Loaded first, libjz.so
+# would bind torch to the system HIP runtime instead of the one torch ships
+# with, and the library's hipGetDevice then finds no device in a process
+# where torch's own calls work.
+import torch  # noqa: F401  (load order only)
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libjz.so")
 HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "jz.h")

@@ -261,10 +261,11 @@ jz_status make_tree_impl(const float *points, const int64_t *offsets, int nsets,
     jz_tree *t = new (std::nothrow) jz_tree();
     if (!t) return jz_fail(JZ_E_OOM, "host allocation failed");
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) {
+    const hipError_t de = hipGetDevice(&dev);
+    if (de != hipSuccess) {
         (void)hipGetLastError();
         delete t;
-        return jz_fail(JZ_E_DEVICE, "no HIP device");
+        return jz_fail(JZ_E_DEVICE, "no HIP device (hipGetDevice: %s)", hipGetErrorString(de));
     }
     t->ac.device = dev;
     if (alloc) {

@@ -269,9 +269,10 @@ jz_status jz_server_create(const jz_server_opts *opts, jz_server **out) {
     if (o.max_batch_points < 1) return jz_fail(JZ_E_INVALID, "max_batch_points must be >= 1");
     if (o.hbm_budget == 0) return jz_fail(JZ_E_INVALID, "hbm_budget must be > 0");
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) {
+    const hipError_t de = hipGetDevice(&dev);
+    if (de != hipSuccess) {
         (void)hipGetLastError();
-        return jz_fail(JZ_E_DEVICE, "no HIP device");
+        return jz_fail(JZ_E_DEVICE, "no HIP device (hipGetDevice: %s)", hipGetErrorString(de));
     }
     jz_server *S = new (std::nothrow) jz_server();
     if (!S) return jz_fail(JZ_E_OOM, "host allocation failed");
