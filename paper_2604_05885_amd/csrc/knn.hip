@@ -106,7 +106,7 @@ __device__ bool stage_list(int2 *__restrict__ gl, int len, uint64_t *S, int scap
 // SORT_MAX).
 constexpr int SORT_MID = 1024;
 constexpr int SORT_MAX = 8192;
-constexpr int SORT_WAVES = 4;
+constexpr int SORT_WAVES = 8;
 
 __global__ __launch_bounds__(64) void k_find_long(const int2 *__restrict__ seg, int n,
                                                   int min_len, int mid, int max_len,
