@@ -1,15 +1,17 @@
 // Exact kNN by a dual walk over the tree planes (paper: kNN section, Alg. 1-3,
 // Eq. 14-16, and the implementation-details subsection on r_low ordering).
 //
-// Level step (one wave per receiving parent; lanes = its children):
+// Level step (one wave per work item: a receiving parent and up to 8 of its
+// children; lanes = those children):
 //   pass 1  FindRmax: register heap of (d_up^2, count); R = smallest radius
 //           whose cumulative count reaches k (Alg. 3)
 //   pass 2  count children pairs with d_low^2 <= R
 //   pass 3  insert them (with r_low = d_low^2) into the next list, at an
 //           offset reserved with one atomic per wave
 // The paper's separate Count / prefix-sum / Insert launches become one kernel.
-// Each receiver's source list is staged in LDS and sorted by r_low so that the
-// early exit "r_low > max over lanes of R" can drop the rest of the list.
+// Each receiver's source list is read in r_low order (sorted in LDS when
+// short, in HBM before the level when long) so that the early exit
+// "r_low > max over lanes of R" can drop the rest of the list.
 //
 // Leaf stage (one wave per receiving leaf; lanes = its query points): source
 // leaves in r_low order, each staged in LDS as float4 (x, y, z, index); every
