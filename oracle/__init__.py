@@ -8,8 +8,13 @@ problem statements and sharing no code with the GPU library:
 * ``knn_bf`` / ``fof_bf``: the definitions written out (all pairs).
 * ``knn_kd`` / ``fof_kd``: exact kd-tree accelerations for large inputs, pinned
   bit-for-bit to the brute-force versions by the tests.
+* ``KdTree``: the kd-tree of ``knn_kd`` kept between calls, answering row
+  ranges, so that a result too large for host memory is compared in chunks.
 * ``components_uf`` / ``components_bfs``: two independent component labelings
   of an explicit edge list.
+* ``knn_f64_report`` / ``fof_f64_report``: binary64 cross-checks (reports, not
+  gates) that list the kNN rows and count the FoF pairs whose decision flips
+  between the fixed float32 expression and the same expression in binary64.
 * :mod:`oracle.planes`: the tree-plane construction of the paper's section on
   the plane-based hierarchy (gap levels, node sizes, split selection), pinned to
   the paper's worked example (Fig. 3).
@@ -65,8 +70,16 @@ def _load():
     lib.jzo_range_rows_bf.argtypes = [_f32p, ctypes.c_int64, ctypes.c_float, _i64p,
                                       ctypes.c_int64, ctypes.c_int64, _i64p, _i32p,
                                       ctypes.c_int]
+    lib.jzo_kd_new.argtypes = [_f32p, ctypes.c_int64, ctypes.c_int]
+    lib.jzo_kd_new.restype = ctypes.c_void_p
+    lib.jzo_kd_knn.argtypes = [ctypes.c_void_p, ctypes.c_int, _i64p, ctypes.c_int64,
+                               ctypes.c_int64, _i32p, _f32p, ctypes.c_int]
+    lib.jzo_kd_free.argtypes = [ctypes.c_void_p]
+    lib.jzo_kd_free.restype = None
+    lib.jzo_fof_f64_report.argtypes = [_f32p, ctypes.c_int64, ctypes.c_float, _i64p, _i64p,
+                                       _i32p, ctypes.c_int]
     for f in ("jzo_knn_bf", "jzo_knn_kd", "jzo_fof_bf", "jzo_fof_kd", "jzo_components_uf",
-              "jzo_components_bfs", "jzo_range_rows_bf"):
+              "jzo_components_bfs", "jzo_range_rows_bf", "jzo_kd_knn", "jzo_fof_f64_report"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -177,26 +190,113 @@ def dist2_f32(p, q) -> np.ndarray:
     return (xx + yy) + zz
 
 
-def near_tie_report(points, idx, margin: int = 4):
+class KdTree:
+    """An exact kd-tree over a fixed point set, answering kNN rows in ranges.
+
+    ``rows(first, count, k)`` gives the same output as :func:`knn_bf` for rows
+    ``first .. first + count - 1``; a large result can so be compared chunk by
+    chunk without holding all of it in host memory.
+    """
+
+    def __init__(self, points, threads: int = 0):
+        self._p = _pts(points)
+        self.n = self._p.shape[0]
+        self._threads = threads or default_threads()
+        self._h = _load().jzo_kd_new(_ptr(self._p, _f32p), self.n, self._threads)
+        if not self._h:
+            raise RuntimeError("oracle kd-tree build failed")
+
+    def rows(self, first: int, count: int, k: int):
+        idx = np.empty((count, k), dtype=np.int32)
+        d2 = np.empty((count, k), dtype=np.float32)
+        rc = _load().jzo_kd_knn(self._h, int(k), None, int(first), int(count),
+                                _ptr(idx, _i32p), _ptr(d2, _f32p), self._threads)
+        if rc != 0:
+            raise RuntimeError("oracle kd-tree query failed (%d)" % rc)
+        return idx, d2
+
+    def select(self, rows, k: int):
+        r = np.ascontiguousarray(rows, dtype=np.int64)
+        idx = np.empty((r.shape[0], k), dtype=np.int32)
+        d2 = np.empty((r.shape[0], k), dtype=np.float32)
+        rc = _load().jzo_kd_knn(self._h, int(k), _ptr(r, _i64p), 0, r.shape[0],
+                                _ptr(idx, _i32p), _ptr(d2, _f32p), self._threads)
+        if rc != 0:
+            raise RuntimeError("oracle kd-tree query failed (%d)" % rc)
+        return idx, d2
+
+    def close(self):
+        if self._h:
+            _load().jzo_kd_free(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        self.close()
+
+
+def knn_f64_report(points, idx, rows=None, margin: int = 4, threads: int = 0):
     """FP64 cross-check of a kNN result (a report, not a gate).
 
-    For each row, the float32 top-k plus the next ``margin`` candidates (taken
-    from a float32 brute-force row of length k + margin) are re-ranked by the
-    exact float64 squared distance and index. Returns the number of rows whose
-    float64 order would differ from the float32 result in membership or order.
+    ``idx`` holds the result rows for ``rows`` (all rows if None). For each
+    row the float32 top k plus the next ``margin`` candidates (an exact float32
+    kNN row of length k + margin) are re-ranked by (binary64 squared distance,
+    index), with the distance evaluated from the float32 coordinates in
+    binary64. Returns the positions (into ``rows``) of the rows whose binary64
+    top k differs from ``idx`` in membership or order: decisions that flip at
+    near-ties of the float32 expression.
     """
     p = _pts(points)
     idx = np.asarray(idx)
     k = idx.shape[1]
-    ext, _ = knn_bf(p, k + margin)
+    r = np.arange(p.shape[0]) if rows is None else np.asarray(rows, dtype=np.int64)
+    if r.shape[0] != idx.shape[0]:
+        raise ValueError("idx must have one row per requested row")
+    with KdTree(p, threads) as kd:
+        ext, _ = kd.select(r, k + margin)
     p64 = p.astype(np.float64)
-    flips = 0
-    for i in range(p.shape[0]):
-        cand = ext[i][ext[i] >= 0]
-        d = ((p64[cand] - p64[i]) ** 2).sum(axis=1)
+    flipped = []
+    for t in range(r.shape[0]):
+        cand = ext[t][ext[t] >= 0]
+        dd = p64[cand] - p64[r[t]]
+        d = (dd[:, 0] * dd[:, 0] + dd[:, 1] * dd[:, 1]) + dd[:, 2] * dd[:, 2]
         order = np.lexsort((cand, d))
         want = cand[order][:k]
-        got = idx[i][idx[i] >= 0]
+        got = idx[t][idx[t] >= 0]
         if want.shape != got.shape or not np.array_equal(want, got):
-            flips += 1
-    return flips
+            flipped.append(t)
+    return np.asarray(flipped, dtype=np.int64)
+
+
+def fof_f64_report(points, b: float, labels=None, threads: int = 0) -> dict:
+    """FP64 cross-check of FoF linking (a report, not a gate).
+
+    Counts the pairs i < j where the float32 test ``dist2 <= fl(b*b)`` and the
+    binary64 test ``d64 <= b*b`` (both from the same float32 coordinates)
+    disagree, and computes the binary64 partition. With ``labels`` (a float32
+    result, smallest-member labels) it also reports whether the partition
+    changes and how many points change group label.
+    """
+    p = _pts(points)
+    n = p.shape[0]
+    o32 = ctypes.c_int64()
+    o64 = ctypes.c_int64()
+    lab64 = np.empty(n, dtype=np.int32)
+    rc = _load().jzo_fof_f64_report(_ptr(p, _f32p), n, float(np.float32(b)), ctypes.byref(o32),
+                                    ctypes.byref(o64), _ptr(lab64, _i32p),
+                                    threads or default_threads())
+    if rc != 0:
+        raise RuntimeError("oracle FoF f64 report failed (%d)" % rc)
+    out = {"pairs_f32_only": int(o32.value), "pairs_f64_only": int(o64.value),
+           "labels_f64": lab64}
+    if labels is not None:
+        lab = np.asarray(labels)
+        moved = int(np.count_nonzero(lab != lab64))
+        out["partition_differs"] = moved > 0
+        out["points_relabelled"] = moved
+    return out

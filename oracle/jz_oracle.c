@@ -373,31 +373,29 @@ static inline int pair_less(float da, int32_t ja, float db, int32_t jb) {
 
 /* Exact kNN with a kd-tree: a subtree is skipped only if its box lower bound
  * is strictly greater than the current k-th distance, so every candidate that
- * could enter the (dist2, j) top-k is evaluated. */
-JZO_API int jzo_knn_kd(const float *pts, int64_t n, int k, const int64_t *rows, int64_t nrows,
-                       int32_t *idx, float *d2, int nthreads) {
-    if (k < 1 || n < 0) return -1;
-    kdtree T;
-    if (kd_build(&T, pts, n, nthreads)) return -2;
-    int64_t R = rows ? nrows : n;
+ * could enter the (dist2, j) top-k is evaluated. Answers rows[0..nrows) or,
+ * with rows == NULL, the consecutive rows first .. first + nrows - 1. */
+static void kd_knn_rows(const kdtree *T, int64_t n, int k, const int64_t *rows, int64_t first,
+                        int64_t nrows, int32_t *idx, float *d2, int nthreads) {
+    const float *pts = T->p;
 #pragma omp parallel num_threads(clamp_threads(nthreads))
     {
         float *bd = (float *)malloc(sizeof(float) * (size_t)k);
         int32_t *bj = (int32_t *)malloc(sizeof(int32_t) * (size_t)k);
         int64_t stack[256];
 #pragma omp for schedule(dynamic, 64)
-        for (int64_t r = 0; r < R; ++r) {
-            int64_t i = rows ? rows[r] : r;
+        for (int64_t r = 0; r < nrows; ++r) {
+            int64_t i = rows ? rows[r] : first + r;
             const float *q = pts + 3 * i;
             int cnt = 0;
             int sp = 0;
             if (n > 0) stack[sp++] = 0;
             while (sp > 0) {
-                kdnode *nd = &T.node[stack[--sp]];
+                const kdnode *nd = &T->node[stack[--sp]];
                 if (cnt == k && box_low(q, nd->lo, nd->hi) > bd[k - 1]) continue;
                 if (nd->left < 0) {
                     for (int64_t t = nd->a; t < nd->b; ++t) {
-                        int32_t j = T.perm[t];
+                        int32_t j = T->perm[t];
                         float d = d2f(q, pts + 3 * (int64_t)j);
                         if (cnt == k && !pair_less(d, j, bd[k - 1], bj[k - 1])) continue;
                         int pos = cnt < k ? cnt : k - 1;
@@ -411,7 +409,7 @@ JZO_API int jzo_knn_kd(const float *pts, int64_t n, int k, const int64_t *rows, 
                         if (cnt < k) ++cnt;
                     }
                 } else {
-                    kdnode *L = &T.node[nd->left], *Rn = &T.node[nd->left + 1];
+                    const kdnode *L = &T->node[nd->left], *Rn = &T->node[nd->left + 1];
                     float dl = box_low(q, L->lo, L->hi), dr = box_low(q, Rn->lo, Rn->hi);
                     /* push the farther child first so the nearer one is visited first */
                     if (dl <= dr) { stack[sp++] = nd->left + 1; stack[sp++] = nd->left; }
@@ -426,8 +424,51 @@ JZO_API int jzo_knn_kd(const float *pts, int64_t n, int k, const int64_t *rows, 
         free(bd);
         free(bj);
     }
+}
+
+JZO_API int jzo_knn_kd(const float *pts, int64_t n, int k, const int64_t *rows, int64_t nrows,
+                       int32_t *idx, float *d2, int nthreads) {
+    if (k < 1 || n < 0) return -1;
+    kdtree T;
+    if (kd_build(&T, pts, n, nthreads)) return -2;
+    kd_knn_rows(&T, n, k, rows, 0, rows ? nrows : n, idx, d2, nthreads);
     kd_free(&T);
     return 0;
+}
+
+/* A kd-tree kept between calls, so that a large input can be answered in row
+ * ranges (the caller then never holds the whole n x k result). The points must
+ * stay valid and unchanged until jzo_kd_free. */
+typedef struct {
+    kdtree T;
+    int64_t n;
+} kdhandle;
+
+JZO_API void *jzo_kd_new(const float *pts, int64_t n, int nthreads) {
+    if (n < 0) return NULL;
+    kdhandle *h = (kdhandle *)malloc(sizeof(kdhandle));
+    if (!h) return NULL;
+    if (kd_build(&h->T, pts, n, nthreads)) { free(h); return NULL; }
+    h->n = n;
+    return h;
+}
+
+/* kNN rows of a kept tree: rows[0..nrows), or first .. first + nrows - 1 when
+ * rows is NULL. Same output as jzo_knn_kd / jzo_knn_bf for those rows. */
+JZO_API int jzo_kd_knn(void *handle, int k, const int64_t *rows, int64_t first, int64_t nrows,
+                       int32_t *idx, float *d2, int nthreads) {
+    kdhandle *h = (kdhandle *)handle;
+    if (!h || k < 1 || nrows < 0) return -1;
+    if (!rows && (first < 0 || first + nrows > h->n)) return -1;
+    kd_knn_rows(&h->T, h->n, k, rows, first, nrows, idx, d2, nthreads);
+    return 0;
+}
+
+JZO_API void jzo_kd_free(void *handle) {
+    kdhandle *h = (kdhandle *)handle;
+    if (!h) return;
+    kd_free(&h->T);
+    free(h);
 }
 
 /* Exact FoF with a kd-tree. For each point i a range search visits the tree:
@@ -511,6 +552,135 @@ JZO_API int jzo_fof_kd(const float *pts, int64_t n, float b, int32_t *label, int
         }
     }
     for (int64_t i = 0; i < n; ++i) label[i] = uf_find(label, (int32_t)i);
+    free(whole);
+    free(loc);
+    kd_free(&T);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* FP64 cross-check of the FoF linking decisions (a report, not a gate)       */
+
+/* The same distance and box bounds evaluated in binary64. Coordinates are
+ * float32, so they convert exactly; every step is correctly rounded and
+ * monotone, so the computed box bounds bracket every member's computed d2d. */
+static inline double d2d(const float *p, const float *q) {
+    double dx = (double)p[0] - (double)q[0];
+    double dy = (double)p[1] - (double)q[1];
+    double dz = (double)p[2] - (double)q[2];
+    return (dx * dx + dy * dy) + dz * dz;
+}
+
+static inline double box_low64(const float *q, const float *lo, const float *hi) {
+    double g[3];
+    for (int a = 0; a < 3; ++a) {
+        double l = (double)lo[a] - (double)q[a];
+        double h = (double)q[a] - (double)hi[a];
+        double m = l > h ? l : h;
+        g[a] = m > 0.0 ? m : 0.0;
+    }
+    return (g[0] * g[0] + g[1] * g[1]) + g[2] * g[2];
+}
+
+static inline double box_up64(const float *q, const float *lo, const float *hi) {
+    double g[3];
+    for (int a = 0; a < 3; ++a) {
+        double l = (double)q[a] - (double)lo[a];
+        double h = (double)hi[a] - (double)q[a];
+        g[a] = l > h ? l : h;
+    }
+    return (g[0] * g[0] + g[1] * g[1]) + g[2] * g[2];
+}
+
+/* For the linking length b, compares the float32 predicate d2f <= fl(b*b)
+ * with the binary64 predicate d2d <= (double)b * (double)b on every pair.
+ * *only32 receives the number of pairs i < j that float32 links and binary64
+ * does not, *only64 the reverse, and label64[n] the FoF labels (smallest
+ * member index) of the binary64 graph, so that the caller can tell whether the
+ * partition itself changes. A kd-tree visit skips boxes where both predicates
+ * fail for every member, and takes whole boxes where both hold for every
+ * member (no disagreement is possible there); only boxes straddling either
+ * threshold are examined pair by pair. */
+JZO_API int jzo_fof_f64_report(const float *pts, int64_t n, float b, int64_t *only32,
+                               int64_t *only64, int32_t *label64, int nthreads) {
+    if (!(b >= 0.0f) || !only32 || !only64) return -1;
+    const float b2 = b * b;
+    const double B = (double)b * (double)b;
+    kdtree T;
+    if (kd_build(&T, pts, n, nthreads)) return -2;
+    int TH = clamp_threads(nthreads);
+    uint8_t *whole = (uint8_t *)calloc((size_t)T.nnode + 1, 1);
+    int32_t *loc = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1) * (size_t)TH);
+    if (!whole || !loc) { free(whole); free(loc); kd_free(&T); return -2; }
+    for (int64_t id = 0; id < T.nnode; ++id) {
+        kdnode *nd = &T.node[id];
+        if (nd->b > nd->a && box_up64(nd->lo, nd->lo, nd->hi) <= B) whole[id] = 1;
+    }
+    int64_t c32 = 0, c64 = 0;
+#pragma omp parallel num_threads(TH) reduction(+ : c32, c64)
+    {
+        int t = omp_get_thread_num();
+        int32_t *par = loc + (size_t)t * (size_t)n;
+        for (int64_t i = 0; i < n; ++i) par[i] = (int32_t)i;
+        int64_t stack[256];
+#pragma omp for schedule(dynamic, 256)
+        for (int64_t i = 0; i < n; ++i) {
+            const float *q = pts + 3 * i;
+            int sp = 0;
+            if (n > 0) stack[sp++] = 0;
+            while (sp > 0) {
+                int64_t id = stack[--sp];
+                kdnode *nd = &T.node[id];
+                if (box_low(q, nd->lo, nd->hi) > b2 && box_low64(q, nd->lo, nd->hi) > B) continue;
+                if (box_up(q, nd->lo, nd->hi) <= b2 && box_up64(q, nd->lo, nd->hi) <= B) {
+                    uf_unite(par, (int32_t)i, T.perm[nd->a]);
+#pragma omp atomic write
+                    whole[id] = 1;
+                    continue;
+                }
+                if (nd->left < 0) {
+                    for (int64_t s = nd->a; s < nd->b; ++s) {
+                        int32_t j = T.perm[s];
+                        if (j == i) continue;
+                        const float *p = pts + 3 * (int64_t)j;
+                        int l32 = d2f(q, p) <= b2;
+                        int l64 = d2d(q, p) <= B;
+                        if (j > i) {
+                            c32 += l32 && !l64;
+                            c64 += l64 && !l32;
+                        }
+                        if (l64) uf_unite(par, (int32_t)i, j);
+                    }
+                } else {
+                    stack[sp++] = nd->left;
+                    stack[sp++] = nd->left + 1;
+                }
+            }
+        }
+    }
+    for (int64_t i = 0; i < n; ++i) label64[i] = (int32_t)i;
+    for (int t = 0; t < TH; ++t) {
+        int32_t *par = loc + (size_t)t * (size_t)n;
+        for (int64_t i = 0; i < n; ++i) uf_unite(label64, (int32_t)i, uf_find(par, (int32_t)i));
+    }
+    {
+        int64_t stack[256];
+        int sp = 0;
+        if (n > 0) stack[sp++] = 0;
+        while (sp > 0) {
+            int64_t id = stack[--sp];
+            kdnode *nd = &T.node[id];
+            if (whole[id]) {
+                int32_t first = T.perm[nd->a];
+                for (int64_t s = nd->a + 1; s < nd->b; ++s) uf_unite(label64, first, T.perm[s]);
+                continue;
+            }
+            if (nd->left >= 0) { stack[sp++] = nd->left; stack[sp++] = nd->left + 1; }
+        }
+    }
+    for (int64_t i = 0; i < n; ++i) label64[i] = uf_find(label64, (int32_t)i);
+    *only32 = c32;
+    *only64 = c64;
     free(whole);
     free(loc);
     kd_free(&T);

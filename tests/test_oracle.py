@@ -326,10 +326,113 @@ def test_range_rows_bf():
         assert cnt[r] == len(want) and np.array_equal(nbr[r, :cnt[r]], want)
 
 
-def test_near_tie_report_runs():
-    p = inputs.lattice(5)  # exact ties everywhere; f32 == f64 here
+# ---------------------------------------------------------------- FP64 reports
+
+def test_knn_f64_report_no_flips_on_exact_lattice():
+    p = inputs.lattice(5)  # every coordinate and dist2 is exact: f32 == f64 == exact
     idx, _ = oracle.knn_bf(p, 7)
-    assert oracle.near_tie_report(p, idx) == 0
+    assert oracle.knn_f64_report(p, idx).size == 0
+
+
+def test_knn_f64_report_flags_a_constructed_tie():
+    """q = origin, b = (1, 2^-13, 0), a = (1, 0, 0): exactly |qa|^2 = 1 and
+    |qb|^2 = 1 + 2^-26, but in float32 fl(1 + 2^-26) = 1, so the two tie and
+    the index puts b (index 1) first. The binary64 order puts a first, so row
+    0 flips in order (k = 3) and in membership (k = 2); rows 1 and 2 do not."""
+    from fractions import Fraction as Fr
+    p = np.array([[0, 0, 0], [1, 2.0 ** -13, 0], [1, 0, 0], [50, 50, 50]], dtype=np.float32)
+    ex = [sum((Fr(float(x)) - Fr(float(y))) ** 2 for x, y in zip(p[0], p[j])) for j in (1, 2)]
+    assert ex[1] < ex[0]                                   # exactly: a is closer
+    d = oracle.dist2_f32(p[0], p[[1, 2]])
+    assert d[0] == d[1]                                    # float32: a tie
+    for k in (2, 3):
+        idx, _ = oracle.knn_bf(p, k)
+        assert idx[0, 1] == 1                              # tie broken by index
+        assert oracle.knn_f64_report(p, idx).tolist() == [0], k
+    # a result already in binary64 order is not flagged
+    idx, _ = oracle.knn_bf(p, 3)
+    idx[0, 1:] = [2, 1]
+    assert oracle.knn_f64_report(p, idx).tolist() == []
+    # sampled rows report positions into the sample
+    idx, _ = oracle.knn_bf(p, 3, rows=[2, 0])
+    assert oracle.knn_f64_report(p, idx, rows=[2, 0]).tolist() == [1]
+
+
+def _threshold_pairs(b, want, count, seed):
+    """Float32 pairs (0,0,0)-(x,y,0) near distance b whose float32 link
+    decision differs from the exact one; want = 'f32' (float32 links, exact
+    does not) or 'exact' (the reverse). The exact value comes from rational
+    arithmetic, and only pairs whose binary64 evaluation is exact are kept."""
+    from fractions import Fraction as Fr
+    f = np.float32
+    B = Fr(float(b)) ** 2
+    b2 = f(b) * f(b)
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < count:
+        x = f(rng.uniform(0.55, 0.85) * float(b))
+        y0 = f(np.sqrt(max(0.0, float(B) - float(x) ** 2)))
+        for s in (-2, -1, 0, 1, 2):
+            y = f(y0 + f(s) * np.spacing(y0))
+            d32 = f(f(x * x) + f(y * y)) + f(0)
+            ex = Fr(float(x)) ** 2 + Fr(float(y)) ** 2
+            if Fr(float(x) * float(x) + float(y) * float(y)) != ex:
+                continue
+            l32, lex = bool(d32 <= b2), ex <= B
+            if (want == "f32" and l32 and not lex) or (want == "exact" and lex and not l32):
+                out.append((x, y))
+                break
+    return out
+
+
+def test_fof_f64_report_counts_constructed_pairs():
+    """Pairs straddling the threshold, checked with exact rational arithmetic:
+    3 that float32 links and binary64 does not, 2 the other way round, each
+    pair 10 apart from the others along z (dz = 0 within a pair, so its
+    distance is exactly that of the constructed pair)."""
+    b = np.float32(1 + 2.0 ** -12)  # fl32(b*b) rounds b^2 down
+    a = _threshold_pairs(b, "f32", 3, seed=1)
+    e = _threshold_pairs(b, "exact", 2, seed=2)
+    pts = []
+    for j, (x, y) in enumerate(a + e):
+        pts += [[0, 0, 10 * j], [x, y, 10 * j]]
+    p = np.array(pts, dtype=np.float32)
+    lab32 = oracle.fof_bf(p, b)
+    # float32 groups the first three pairs, binary64 the last two
+    assert lab32.tolist() == [0, 0, 2, 2, 4, 4, 6, 7, 8, 9]
+    rep = oracle.fof_f64_report(p, b, labels=lab32)
+    assert rep["pairs_f32_only"] == 3 and rep["pairs_f64_only"] == 2
+    assert rep["labels_f64"].tolist() == [0, 1, 2, 3, 4, 5, 6, 6, 8, 8]
+    assert rep["partition_differs"] and rep["points_relabelled"] == 5
+
+
+def test_fof_f64_report_agrees_away_from_ties():
+    """A lattice (exact arithmetic) and a random set: no disagreements on the
+    lattice; on any set the binary64 labels equal the float32 ones exactly
+    when no pair disagrees."""
+    p = inputs.lattice(6)
+    for b in (2.0 ** -4, 2.0 ** -4 * 1.5):
+        rep = oracle.fof_f64_report(p, b, labels=oracle.fof_bf(p, b))
+        assert rep["pairs_f32_only"] == 0 and rep["pairs_f64_only"] == 0
+        assert not rep["partition_differs"]
+    q = inputs.clustered(3000, 8, 5)
+    b = inputs.linking_length(3000, 0.5)
+    rep = oracle.fof_f64_report(q, b, labels=oracle.fof_kd(q, b))
+    if rep["pairs_f32_only"] == 0 and rep["pairs_f64_only"] == 0:
+        assert not rep["partition_differs"]
+
+
+def test_kd_handle_rows_equal_bf():
+    p = inputs.clustered(5000, 8, 9)
+    want_i, want_d = oracle.knn_bf(p, 12)
+    with oracle.KdTree(p) as kd:
+        for first, count in ((0, 1), (0, 1000), (1000, 2500), (4999, 1)):
+            gi, gd = kd.rows(first, count, 12)
+            assert np.array_equal(gi, want_i[first:first + count])
+            assert np.array_equal(gd.view(np.uint32), want_d[first:first + count].view(np.uint32))
+        rows = [4, 4000, 17]
+        gi, gd = kd.select(rows, 12)
+        assert np.array_equal(gi, want_i[rows])
 
 
 # ---------------------------------------------------------------- generators
