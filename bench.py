@@ -11,7 +11,10 @@ The line also carries:
   roofline     the dominant kernel (leaf-stage kNN), timed with HIP events on
                the stream it runs on, against the FP32 VALU rate for plain
                (non-fused, non-packed) add/mul: 256 CU * 64 lanes * 2.4 GHz
-  cpu_baseline the CPU oracle (exact kd-tree kNN + FoF) on the host cores
+  cpu_baseline the CPU oracle (exact kd-tree kNN + FoF) on the host cores,
+               and the last step's GPU result compared with it
+  fp64_report  binary64 cross-check of that result (sampled kNN rows, every
+               FoF pair): decisions that flip at float32 near-ties
   breakdown    per-call device times (build / knn / fof) and walk statistics
 """
 from __future__ import annotations
@@ -50,10 +53,10 @@ def parse():
                          "per-set launches; served: Poisson request stream")
     ap.add_argument("--sets", type=int, default=4096, help="batched: number of sets")
     ap.add_argument("--rate", type=float, default=2000.0, help="served: requests per second")
-    ap.add_argument("--duration", type=float, default=10.0, help="served: seconds of arrivals")
-    ap.add_argument("--measure-after", type=float, default=2.0,
-                    help="served: arrivals before this time (s) are warm-up")
-    ap.add_argument("--pool", type=int, default=64, help="served: distinct point sets")
+    ap.add_argument("--duration", type=float, default=30.0,
+                    help="served: measured seconds of arrivals (after the warm-up)")
+    ap.add_argument("--measure-after", type=float, default=5.0,
+                    help="served: seconds of warm-up arrivals before the measured ones")
     ap.add_argument("--streams", type=int, default=4, help="served: server worker streams")
     return ap.parse_args()
 
@@ -170,16 +173,27 @@ def main():
         t1 = time.perf_counter()
         ol = oracle.fof_kd(pts, b, threads=threads)
         t2 = time.perf_counter()
-        # the timed GPU result of the last step, checked on a sample of rows
-        gi = idx.cpu().numpy()
-        rows = np.random.default_rng(0).choice(n, 4096, replace=False)
-        ok = bool(np.array_equal(gi[rows], oi[rows]) and
-                  np.array_equal(lab.cpu().numpy(), ol))
+        # the timed GPU result of the last step against the oracle: every kNN
+        # row and every label
+        gi, gd, gl = idx.cpu().numpy(), d2.cpu().numpy(), lab.cpu().numpy()
+        ok = bool(np.array_equal(gi, oi) and np.array_equal(gd.view(np.uint32), od.view(np.uint32))
+                  and np.array_equal(gl, ol))
         out["cpu_baseline"] = {"value": n / (t2 - t0), "unit": "points/s", "cores": threads,
                                "kind": "oracle",
                                "sample": "the full benchmark set (N=2^24): exact kd-tree kNN k=%d "
                                          "(%.1fs) + FoF (%.1fs)" % (k, t1 - t0, t2 - t1),
                                "gpu_matches_oracle": ok}
+        # binary64 cross-check of the same result (a report, not a gate):
+        # sampled kNN rows re-ranked in binary64, every FoF pair's decision
+        rows = np.random.default_rng(0).choice(n, 4096, replace=False)
+        flips = oracle.knn_f64_report(pts, gi[rows], rows=rows, threads=threads)
+        rep = oracle.fof_f64_report(pts, b, labels=gl, threads=threads)
+        out["fp64_report"] = {"knn_rows_checked": int(rows.size),
+                              "knn_rows_flipped": int(flips.size),
+                              "fof_pairs_f32_only": rep["pairs_f32_only"],
+                              "fof_pairs_f64_only": rep["pairs_f64_only"],
+                              "fof_partition_differs": rep["partition_differs"],
+                              "fof_points_relabelled": rep["points_relabelled"]}
     print(json.dumps(out), flush=True)
 
 
@@ -290,103 +304,165 @@ def batched(args):
 def served(args):
     """Open-loop Poisson stream of kNN / FoF requests (k in {8,16,32}, alpha in
     {0.1,0.2}, N log-uniform in [2^12, 2^22]) through the continuous-batching
-    server, against the same stream through per-request launches (one request
-    per batch, one worker). Latency = completion - scheduled arrival."""
+    server. Every request gets a fresh clustered set drawn on the GPU from its
+    own seed (on the client's stream, right before submission: the server
+    orders the request after it). Latency = completion - scheduled arrival, so
+    queueing and any client delay count. Reported beside it: the same stream
+    at 60% of the rate, and per-request plain launches (FIFO, one at a time)
+    run back to back on the same request mix."""
+    import threading
+
     import numpy as np
     import torch
 
     from paper_2604_05885_amd import api, inputs
 
     torch.cuda.set_device(0)
-    rng = np.random.default_rng(5)
-    t0 = time.time()
-    pool = []
-    for i in range(args.pool):
-        nn = int(np.floor(2.0 ** rng.uniform(12, 22)))
-        p = inputs.clustered(nn, max(1, int(round(4096 * nn / 2.0 ** 24))), seed=5_000_000 + i)
-        pool.append(torch.from_numpy(p).cuda())
-    outs = [{kk: (torch.empty((q.shape[0], kk), dtype=torch.int32, device="cuda"),
-                  torch.empty((q.shape[0], kk), dtype=torch.float32, device="cuda"))
-             for kk in (8, 16, 32)} for q in pool]
-    labs = [torch.empty(q.shape[0], dtype=torch.int32, device="cuda") for q in pool]
-    torch.cuda.synchronize()
-    print("# pool of %d sets (%d points) in %.1fs" % (args.pool, sum(q.shape[0] for q in pool),
-                                                      time.time() - t0), file=sys.stderr, flush=True)
-    def schedule(rate, duration, seed):
-        rs = inputs.served_requests(int(rate * duration), seed=seed, rate_hz=rate)
-        pick = np.random.default_rng(seed + 1)
-        for r in rs:
-            r["set"] = int(pick.integers(args.pool))
-        return rs
+    client = torch.cuda.Stream()
 
-    reqs = schedule(args.rate, args.duration, 5)
+    def make(r):
+        with torch.cuda.stream(client):
+            p = inputs.clustered_device(r["n"], r["clumps"], r["seed"], stream=client)
+            if r["op"] == "knn":
+                out = (torch.empty((r["n"], r["k"]), dtype=torch.int32, device="cuda"),
+                       torch.empty((r["n"], r["k"]), dtype=torch.float32, device="cuda"))
+            else:
+                out = (torch.empty(r["n"], dtype=torch.int32, device="cuda"),)
+        return p, out
 
-    def run(streams, max_sets, reqs=reqs, measure_after=args.measure_after):
-        S = api.Server(streams=streams, max_batch_sets=max_sets, hbm_budget=int(200e9))
-        # warm the library (kernels, pool, learned list sizes)
-        for q, o, l in zip(pool[:8], outs[:8], labs[:8]):
-            S.wait(S.submit_knn(q, 16, *o[16]))
-            S.wait(S.submit_fof(q, inputs.linking_length(q.shape[0]), l))
-        t_start = api.now_ns() + int(0.05e9)
-        tickets = []
+    def submit(S, r, p, out):
+        with torch.cuda.stream(client):
+            if r["op"] == "knn":
+                return S.submit_knn(p, r["k"], *out)
+            return S.submit_fof(p, inputs.linking_length(r["n"], r["alpha"]), *out)
+
+    def run_open(rate, warm, measure, seed):
+        reqs = inputs.served_requests(int(rate * (warm + measure)), seed=seed, rate_hz=rate)
+        S = api.Server(streams=args.streams, max_batch_sets=4096, hbm_budget=int(200e9))
+        for r in reqs[:16]:  # warm the library (kernels, pool, learned list sizes)
+            p, out = make(r)
+            S.wait(submit(S, r, p, out))
+        torch.cuda.synchronize()
+        done = []          # (ticket, due_ns, request)
+        results = {}
+        lock = threading.Condition()
+        state = {"n_sub": 0, "stop": False, "collected": 0}
+        aborted = False
+
+        def collector():
+            i = 0
+            while True:
+                state["collected"] = i
+                with lock:
+                    while i >= state["n_sub"] and not state["stop"]:
+                        lock.wait()
+                    if i >= state["n_sub"]:
+                        return
+                    tk, due, r = done[i]
+                try:
+                    _, t_done = S.wait(tk)
+                    results[i] = (t_done, None)
+                except api.JzError as e:
+                    results[i] = (None, str(e))
+                S.release(tk)
+                i += 1
+
+        th = threading.Thread(target=collector)
+        th.start()
+        t0 = api.now_ns() + int(0.05e9)
+        late_max = 0.0
+        backlog = []
         for r in reqs:
-            due = t_start + int(r["t"] * 1e9)
+            due = t0 + int(r["t"] * 1e9)
             while api.now_ns() < due:
                 pass
-            q = pool[r["set"]]
-            if r["op"] == "knn":
-                tk = S.submit_knn(q, r["k"], *outs[r["set"]][r["k"]])
-            else:
-                tk = S.submit_fof(q, inputs.linking_length(q.shape[0], r["alpha"]),
-                                  labs[r["set"]])
-            tickets.append((tk, due, r))
-        lat, last_done, first_due, npts = [], 0, None, 0
-        failed, first_error = 0, None
-        for tk, due, r in tickets:
-            try:
-                _, done_ns = S.wait(tk)
-            except api.JzError as e:  # reported, not hidden: a failed request is a bug
-                failed += 1
-                first_error = first_error or str(e)
-                S.release(tk)
-                continue
-            S.release(tk)
-            if r["t"] >= measure_after:
-                lat.append((done_ns - due) / 1e6)
-                last_done = max(last_done, done_ns)
-                first_due = due if first_due is None else min(first_due, due)
-                npts += pool[r["set"]].shape[0]
+            late_max = max(late_max, (api.now_ns() - due) / 1e6)
+            if state["n_sub"] - state["collected"] > 2000:
+                # more than a second of arrivals outstanding: the device does
+                # not keep up; stop before their buffers exhaust memory
+                aborted = True
+                break
+            p, out = make(r)
+            tk = submit(S, r, p, out)
+            with lock:
+                done.append((tk, due, r))
+                state["n_sub"] += 1
+                lock.notify()
+            if len(done) % 500 == 0:
+                backlog.append((r["t"], S.stats()["pending"]))
+        with lock:
+            state["stop"] = True
+            lock.notify()
+        th.join()
         st = S.stats()
         S.close()
+        lat, npts, first_due, last_done, failed, err = [], 0, None, 0, 0, None
+        for i, (tk, due, r) in enumerate(done):
+            t_done, e = results[i]
+            if e is not None:
+                failed += 1
+                err = err or e
+                continue
+            if r["t"] >= warm:
+                lat.append((t_done - due) / 1e6)
+                npts += r["n"]
+                first_due = due if first_due is None else min(first_due, due)
+                last_done = max(last_done, t_done)
         lat = np.array(lat)
         span = (last_done - first_due) / 1e9
-        return {"solves_per_s": len(lat) / span, "points_per_s": npts / span,
-                "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-                "requests": len(lat), "batches": st["batches"],
-                "max_batch": st["max_batch_sets_seen"], "failed": failed,
-                "first_error": first_error}
+        half = [b for t, b in backlog if t >= warm]
+        return {"offered_req_per_s": rate, "solves_per_s": len(lat) / span,
+                "points_per_s": npts / span, "p50_ms": float(np.percentile(lat, 50)),
+                "p99_ms": float(np.percentile(lat, 99)), "requests": int(len(lat)),
+                "batches": st["batches"], "max_batch": st["max_batch_sets_seen"],
+                "failed": failed, "first_error": err, "client_late_max_ms": late_max,
+                "pending_first_half_max": int(max(half[:len(half) // 2] or [0])),
+                "pending_second_half_max": int(max(half[len(half) // 2:] or [0])),
+                "aborted_backlog": aborted,
+                "sustained": bool(not aborted and len(lat) / span >= 0.97 * rate)}
 
-    cont = run(args.streams, 4096)
-    fifo = run(1, 1)
-    # When the offered rate exceeds what the device sustains, the queue grows
-    # for the whole run and p50/p99 measure that backlog; so the server is
-    # also run at 60% of the solves/s it sustained, where latency is service
-    # time plus batching delay.
-    light_rate = 0.6 * cont["solves_per_s"]
-    light = run(args.streams, 4096, reqs=schedule(light_rate, 6.0, 7), measure_after=1.0)
-    light["offered_req_per_s"] = light_rate
+    def run_fifo(count, seed):
+        """Per-request plain launches (build + kNN / FoF), one at a time on
+        one stream, back to back: the device time of the same mix without
+        batching or overlap."""
+        reqs = inputs.served_requests(count, seed=seed, rate_hz=2000.0)
+        stream = torch.cuda.current_stream()
+        data = [make(r) for r in reqs[:64]]
+        torch.cuda.synchronize()
+        total_t, npts = 0.0, 0
+        for i, r in enumerate(reqs):
+            p, out = make(r) if i >= 64 else data[i]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            t = api.jz_build(p, stream=stream)
+            if r["op"] == "knn":
+                t.knn(r["k"], *out, stream=stream)
+            else:
+                t.fof(inputs.linking_length(r["n"], r["alpha"]), *out, stream=stream)
+            t.free()
+            total_t += time.perf_counter() - t0
+            npts += r["n"]
+        return {"solves_per_s": count / total_t, "points_per_s": npts / total_t,
+                "requests": count}
+
+    cont = run_open(args.rate, args.measure_after, args.duration, seed=5)
+    print("# continuous batching done", file=sys.stderr, flush=True)
+    light = run_open(0.6 * args.rate, 2.0, 10.0, seed=7)
+    print("# 60%% load done", file=sys.stderr, flush=True)
+    fifo = run_fifo(1000, seed=9)
     out = {
         "metric": "served kNN/FoF solves/s with p50/p99 latency (open-loop Poisson arrivals)",
         "value": cont["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
-        "steps": len(reqs), "warmup": 0, "ms_per_step": None, "higher_is_better": True,
+        "steps": cont["requests"], "warmup": 0, "ms_per_step": None, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "Poisson %g req/s for %gs (first %gs warm-up); each request kNN "
-                               "(k in {8,16,32}) or FoF (alpha in {0.1,0.2}) on one of %d clustered "
-                               "sets with N log-uniform in [2^12, 2^22]; HBM budget 200 GB"
-                               % (args.rate, args.duration, args.measure_after, args.pool)},
+        "config": {"workload": "Poisson %g req/s for %gs after %gs warm-up; each request kNN "
+                               "(k in {8,16,32}) or FoF (alpha in {0.1,0.2}) on a fresh clustered "
+                               "set drawn on the GPU from its own seed, N log-uniform in "
+                               "[2^12, 2^22]; HBM budget 200 GB"
+                               % (args.rate, args.duration, args.measure_after)},
         "continuous_batching": cont,
-        "per_request_fifo": fifo,
-        "continuous_batching_at_60pct_of_sustained": light,
+        "continuous_batching_at_60pct": light,
+        "per_request_fifo_back_to_back": fifo,
         "speedup_vs_fifo": cont["solves_per_s"] / fifo["solves_per_s"],
     }
     print(json.dumps(out), flush=True)

@@ -48,7 +48,7 @@ typedef enum jz_status {
     JZ_OK = 0,
     JZ_E_INVALID = 1,      /* bad argument (null pointer, n out of range, k < 1, b < 0 or NaN) */
     JZ_E_NONFINITE = 2,    /* an input coordinate is NaN or infinite */
-    JZ_E_UNSUPPORTED = 3,  /* k > 32 */
+    JZ_E_UNSUPPORTED = 3,  /* k > JZ_MAX_K */
     JZ_E_CAPACITY = 4,     /* interaction list overflow with auto_regrow = 0 */
     JZ_E_OOM = 5,          /* device allocation failed */
     JZ_E_DEVICE = 6        /* a HIP runtime error */
@@ -98,12 +98,18 @@ typedef struct jz_tree jz_tree;
 JZ_API jz_status jz_build(const float *points, int64_t n, void *stream, const jz_build_opts *opts,
                    const jz_allocator *alloc, jz_tree **out);
 
+/* Largest k of jz_knn. */
+#define JZ_MAX_K 256
+
 /* Exact k nearest neighbours of every point, self included (paper: kNN
  * section, Alg. 1-3 and the LeafToLeaf kernel). Row i of idx[n][k] holds the
  * input indices of the k points closest to point i (input order), ascending by
  * (dist2, index); dist2[n][k] holds their squared distances. If k > n the row
- * tail is idx = -1, dist2 = +inf. k in [1, 32] (k > 32: JZ_E_UNSUPPORTED).
- * idx and dist2 are device buffers of n*k elements. */
+ * tail is idx = -1, dist2 = +inf. k in [1, JZ_MAX_K] (larger: JZ_E_UNSUPPORTED);
+ * k > 32 runs the leaf stage in passes of 32 neighbours, each continuing after
+ * the last (dist2, index) of the pass before, as the paper's LeafToLeaf does
+ * above its 32-neighbour limit. idx and dist2 are device buffers of n*k
+ * elements. */
 JZ_API jz_status jz_knn(jz_tree *t, int k, int32_t *idx, float *dist2, void *stream);
 
 /* Friends-of-friends groups (paper: FoF section, Eq. 18): connected
@@ -114,6 +120,12 @@ JZ_API jz_status jz_fof(jz_tree *t, float b, int32_t *label, void *stream);
 
 /* Release the tree and its device memory (NULL is ignored). */
 JZ_API void jz_tree_free(jz_tree *t);
+
+/* Bytes of device memory the tree holds between calls (sorted points, node
+ * planes, splits, top-level lists; 0 for NULL). Scratch memory of a
+ * jz_knn / jz_fof call is taken from the allocator during the call and
+ * returned before it ends. */
+JZ_API int64_t jz_tree_size(const jz_tree *t);
 
 /* ---- batched solving: many independent point sets in one tree ----------
  * (the paper motivates repeated evaluations, e.g. simulation-based inference,
@@ -133,13 +145,44 @@ JZ_API jz_status jz_forest_build(const float *points, const int64_t *offsets, in
  * finite values >= 0). label[n] is set-local (smallest index within the set). */
 JZ_API jz_status jz_forest_fof(jz_tree *t, const float *b, int32_t *label, void *stream);
 
+/* ---- FoF catalogue ---------------------------------------------------------
+ * (paper: FoF section, catalogue reduction) The groups of jz_fof with
+ * linking length b, brought into group order and summarized. Group order is
+ * a stable sort of the input indices by group label: groups follow their
+ * labels (smallest member index) in ascending order, and each group is one
+ * contiguous block of ascending input indices (the input-order counterpart
+ * of the paper's sort into group order, since every result of this library
+ * is in input order). Per group with at least min_members points: */
+typedef struct jz_group {
+    int32_t label;      /* the group's label: its smallest member index */
+    int32_t count;      /* members (the mass, at unit point mass) */
+    int64_t first;      /* offset of the group's block in order[] */
+    double cm[3];       /* centre of mass: mean member position (binary64 sums) */
+    double vcm[3];      /* centre-of-mass velocity: mean member velocity (0 without vel) */
+    double r_inertia;   /* inertia radius: RMS distance of the members from cm */
+} jz_group;
+
+/* On a tree from jz_build (one set): label[n] (DEVICE, may be NULL) receives
+ * the labels as jz_fof gives them; order[n] (DEVICE) the input indices in
+ * group order; groups[max_groups] (DEVICE) the groups with >= min_members
+ * (>= 1) points, in label order; *ngroups (HOST) their number. vel: DEVICE
+ * float32 [n][3] member velocities in input order, or NULL. If more than
+ * max_groups groups qualify, returns JZ_E_CAPACITY with *ngroups set to the
+ * number needed (label and order are complete then). The sums are binary64
+ * in an order that may vary between calls (atomics), so cm, vcm and
+ * r_inertia may differ in the last bits from run to run; label, order,
+ * count, first are exact. */
+JZ_API jz_status jz_fof_catalogue(jz_tree *t, float b, int min_members, const float *vel,
+                                  int32_t *label, int32_t *order, jz_group *groups,
+                                  int64_t max_groups, int64_t *ngroups, void *stream);
+
 /* ---- autotuning -----------------------------------------------------------
  * Time the build plus the requested operations on the caller's workload for
  * each candidate setting (leaf_max in {32, 48, 64} x coarsen in {4, 8}; other
  * fields taken from *base or the defaults) and return the fastest in *best
  * and its time (ms, best of two runs) in *best_ms. points / offsets / nsets
  * as for jz_forest_build (offsets may be NULL for one set of n points; then
- * nsets is n). k in [1, 32] runs kNN, k = 0 skips it; b (HOST, one value per
+ * nsets is n). k in [1, JZ_MAX_K] runs kNN, k = 0 skips it; b (HOST, one value per
  * set) runs FoF, NULL skips it. The winner is remembered for the signature
  * (k, FoF or not, number of sets, log2 of the point count) for the rest of
  * the process, and later calls with that signature return it without
@@ -164,13 +207,18 @@ enum { JZ_OP_KNN = 0, JZ_OP_FOF = 1 };
 
 typedef struct jz_request {
     int op;                  /* JZ_OP_KNN or JZ_OP_FOF */
-    int k;                   /* kNN: neighbours per point, [1, 32] */
+    int k;                   /* kNN: neighbours per point, [1, JZ_MAX_K] */
     float b;                 /* FoF: linking length, finite, >= 0 */
     const float *points;     /* DEVICE [n][3]; must stay valid until the request is done */
     int64_t n;               /* [0, 2^31-2] */
     int32_t *idx;            /* kNN output, DEVICE [n][k] (input order, indices within the request) */
     float *dist2;            /* kNN output, DEVICE [n][k] */
     int32_t *label;          /* FoF output, DEVICE [n] (smallest index within the request's group) */
+    void *stream;            /* the caller's hipStream_t (NULL = default stream): jz_server_submit
+                                records an event on it, and the request's work starts only after
+                                everything queued on it before the call (e.g. the kernels that
+                                write `points`). Results are complete once the request is done;
+                                the caller orders its later reads after jz_server_wait / _poll. */
 } jz_request;
 
 typedef struct jz_server_opts {
@@ -188,8 +236,11 @@ JZ_API void jz_server_default_opts(jz_server_opts *o);
 JZ_API jz_status jz_server_create(const jz_server_opts *opts, jz_server **out);
 
 /* Queue a request (copied; the buffers it points to are not). *ticket
- * identifies it. Invalid requests, and requests whose estimated footprint
- * exceeds the whole budget, are rejected here (JZ_E_INVALID / JZ_E_OOM). */
+ * identifies it. The request reads its points only after the work queued on
+ * r->stream before this call has finished (an event is recorded there), so
+ * points still being written on that stream are safe to submit. Invalid
+ * requests, and requests whose estimated footprint exceeds the whole budget,
+ * are rejected here (JZ_E_INVALID / JZ_E_OOM). */
 JZ_API jz_status jz_server_submit(jz_server *s, const jz_request *r, uint64_t *ticket);
 
 /* *done = 1 once the request's outputs are complete on the device; then
@@ -243,6 +294,12 @@ typedef struct jz_stats {
                                         LDS, put in r_low order (in the wave's LDS scratch up to
                                         1024 entries, beforehand in HBM up to sort_max) */
     int64_t lists_unordered;         /* kNN leaf stage: lists longer than sort_max, read unordered */
+    /* kNN lists put in r_low order in HBM before they are walked, by the sorter
+     * for lists of up to 1024 entries ([0]) and by the one for longer lists, up
+     * to sort_max ([1]); index p < JZ_MAX_PLANES: the lists of plane p + 1 read
+     * by walk level p; index JZ_MAX_PLANES: the leaf lists read by the leaf
+     * stage (only those longer than it sorts itself, 1024 entries). */
+    int64_t lists_presorted[JZ_MAX_PLANES + 1][2];
 } jz_stats;
 
 /* Statistics of the tree and of its last kNN / FoF call. */
@@ -267,7 +324,7 @@ JZ_API void jz_release_cached(void);
 /* Thread-local message of the last error (empty string if none). */
 JZ_API const char *jz_last_error(void);
 
-/* ABI version of this header (2). */
+/* ABI version of this header (3). */
 JZ_API int jz_abi_version(void);
 
 #ifdef __cplusplus

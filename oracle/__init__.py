@@ -300,3 +300,42 @@ def fof_f64_report(points, b: float, labels=None, threads: int = 0) -> dict:
         out["partition_differs"] = moved > 0
         out["points_relabelled"] = moved
     return out
+
+
+def fof_catalogue(points, labels, min_members: int = 20, velocities=None) -> dict:
+    """FoF catalogue reduction (the paper's FoF section, catalogue reduction),
+    written out in binary64 with numpy.
+
+    Group order: a stable sort of the input indices by group label, so groups
+    follow their labels (the smallest member index) in ascending order and
+    each group is one contiguous block of ascending input indices. For every
+    group with at least ``min_members`` points, in label order: its label,
+    the offset of its block in ``order``, its member count (the mass, at unit
+    point mass), the centre of mass (mean position), the inertia radius
+    (root-mean-square distance of the members from the centre of mass) and,
+    with ``velocities``, the centre-of-mass velocity (mean velocity).
+    """
+    p = _pts(points).astype(np.float64)
+    lab = np.asarray(labels, dtype=np.int64)
+    order = np.argsort(lab, kind="stable").astype(np.int32)
+    gl, first, count = np.unique(lab[order], return_index=True, return_counts=True)
+    keep = count >= min_members
+    out = {"order": order, "label": gl[keep].astype(np.int32),
+           "first": first[keep].astype(np.int64), "count": count[keep].astype(np.int64)}
+    cm = np.zeros((int(keep.sum()), 3))
+    r = np.zeros(int(keep.sum()))
+    vcm = np.zeros((int(keep.sum()), 3)) if velocities is not None else None
+    v = None if velocities is None else np.asarray(velocities, dtype=np.float32).astype(np.float64)
+    for g, (f, c) in enumerate(zip(out["first"], out["count"])):
+        members = order[f:f + c]
+        x = p[members]
+        cm[g] = x.sum(axis=0) / c
+        d = x - cm[g]
+        r[g] = np.sqrt((d * d).sum() / c)
+        if v is not None:
+            vcm[g] = v[members].sum(axis=0) / c
+    out["cm"] = cm
+    out["r_inertia"] = r
+    if vcm is not None:
+        out["vcm"] = vcm
+    return out

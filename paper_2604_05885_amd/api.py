@@ -51,7 +51,8 @@ class Stats(ctypes.Structure):
                 ("evaluations", ctypes.c_double), ("leaf_ms", ctypes.c_double),
                 ("total_ms", ctypes.c_double), ("reruns", ctypes.c_int),
                 ("insert_rounds", ctypes.c_int64), ("tile_steps", ctypes.c_int64),
-                ("lists_sorted_long", ctypes.c_int64), ("lists_unordered", ctypes.c_int64)]
+                ("lists_sorted_long", ctypes.c_int64), ("lists_unordered", ctypes.c_int64),
+                ("lists_presorted", (ctypes.c_int64 * 2) * (MAX_PLANES + 1))]
 
     def as_dict(self) -> dict:
         P = self.planes
@@ -63,7 +64,9 @@ class Stats(ctypes.Structure):
                 "total_ms": self.total_ms, "reruns": self.reruns,
                 "insert_rounds": self.insert_rounds, "tile_steps": self.tile_steps,
                 "lists_sorted_long": self.lists_sorted_long,
-                "lists_unordered": self.lists_unordered}
+                "lists_unordered": self.lists_unordered,
+                "lists_presorted_walk": [list(self.lists_presorted[q]) for q in range(max(P - 1, 0))],
+                "lists_presorted_leaf": list(self.lists_presorted[MAX_PLANES])}
 
 
 class Allocator(ctypes.Structure):
@@ -77,7 +80,8 @@ class Allocator(ctypes.Structure):
 class Request(ctypes.Structure):
     _fields_ = [("op", ctypes.c_int), ("k", ctypes.c_int), ("b", ctypes.c_float),
                 ("points", ctypes.c_void_p), ("n", ctypes.c_int64), ("idx", ctypes.c_void_p),
-                ("dist2", ctypes.c_void_p), ("label", ctypes.c_void_p)]
+                ("dist2", ctypes.c_void_p), ("label", ctypes.c_void_p),
+                ("stream", ctypes.c_void_p)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -96,6 +100,16 @@ class ServeStats(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class Group(ctypes.Structure):
+    _fields_ = [("label", ctypes.c_int32), ("count", ctypes.c_int32), ("first", ctypes.c_int64),
+                ("cm", ctypes.c_double * 3), ("vcm", ctypes.c_double * 3),
+                ("r_inertia", ctypes.c_double)]
+
+
+GROUP_DTYPE = np.dtype([("label", np.int32), ("count", np.int32), ("first", np.int64),
+                        ("cm", np.float64, 3), ("vcm", np.float64, 3), ("r_inertia", np.float64)])
+assert GROUP_DTYPE.itemsize == ctypes.sizeof(Group)
+
 JZ_OP_KNN, JZ_OP_FOF = 0, 1
 
 _vp = ctypes.c_void_p
@@ -109,6 +123,7 @@ _SIGS = {
     "jz_knn": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp]),
     "jz_fof": (ctypes.c_int, [_vp, ctypes.c_float, _vp, _vp]),
     "jz_tree_free": (None, [_vp]),
+    "jz_tree_size": (ctypes.c_int64, [_vp]),
     "jz_forest_build": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int, _vp,
                                        ctypes.POINTER(BuildOpts), ctypes.POINTER(Allocator),
                                        ctypes.POINTER(_vp)]),
@@ -128,6 +143,8 @@ _SIGS = {
     "jz_server_stats": (ctypes.c_int, [_vp, ctypes.POINTER(ServeStats)]),
     "jz_server_destroy": (None, [_vp]),
     "jz_now_ns": (ctypes.c_int64, []),
+    "jz_fof_catalogue": (ctypes.c_int, [_vp, ctypes.c_float, ctypes.c_int, _vp, _vp, _vp, _vp,
+                                        ctypes.c_int64, _i64p, _vp]),
     "jz_autotune": (ctypes.c_int, [_vp, _i64p, ctypes.c_int64, ctypes.c_int,
                                    ctypes.POINTER(ctypes.c_float), _vp, ctypes.POINTER(BuildOpts),
                                    ctypes.POINTER(BuildOpts), ctypes.POINTER(ctypes.c_double)]),
@@ -187,6 +204,66 @@ def _points(points):
     return points.contiguous()
 
 
+class TorchAllocator:
+    """A ``jz_allocator`` that takes the library's device memory from torch's
+    caching allocator (so it shows in ``torch.cuda.memory_allocated`` and is
+    reused by torch after the library frees it).
+
+    The library frees every block with the stream it was last used on; its
+    calls are synchronous, so that work has finished when a block returns to
+    torch. ``live`` counts the blocks currently handed out.
+    """
+
+    def __init__(self, device=None):
+        import torch
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        self.live = 0
+        self.allocs = 0
+        self._alloc_cb = Allocator._fields_[1][1](self._alloc)
+        self._free_cb = Allocator._fields_[2][1](self._free)
+        self.struct = Allocator(None, self._alloc_cb, self._free_cb)
+
+    def _alloc(self, ctx, nbytes, stream):
+        import torch
+        try:
+            p = torch.cuda.caching_allocator_alloc(int(nbytes), self.device, int(stream or 0))
+        except Exception:  # out of memory: the library reports JZ_E_OOM
+            return None
+        self.live += 1
+        self.allocs += 1
+        return p
+
+    def _free(self, ctx, ptr, nbytes, stream):
+        import torch
+        torch.cuda.caching_allocator_delete(int(ptr))
+        self.live -= 1
+
+
+_torch_allocators = {}
+
+
+def torch_allocator(device=None) -> TorchAllocator:
+    """The process's TorchAllocator for a device (created on first use)."""
+    import torch
+    dev = torch.cuda.current_device() if device is None else int(device)
+    if dev not in _torch_allocators:
+        _torch_allocators[dev] = TorchAllocator(dev)
+    return _torch_allocators[dev]
+
+
+def _alloc_arg(allocator):
+    """ctypes argument for an allocator: None = the library's own pool,
+    "torch" = torch's caching allocator, or an object with a ``struct``
+    (jz_allocator) attribute."""
+    if allocator is None:
+        return None, None
+    if isinstance(allocator, str):
+        if allocator != "torch":
+            raise ValueError("allocator must be None, 'torch' or an allocator object")
+        allocator = torch_allocator()
+    return ctypes.byref(allocator.struct), allocator
+
+
 def jz_set_profiling(on: bool):
     lib.jz_set_profiling(1 if on else 0)
 
@@ -198,11 +275,13 @@ def jz_release_cached():
 class Tree:
     """A built tree (owns device memory until :meth:`free`)."""
 
-    def __init__(self, handle: ctypes.c_void_p, n: int, nsets: int = 1, offsets=None):
+    def __init__(self, handle: ctypes.c_void_p, n: int, nsets: int = 1, offsets=None,
+                 allocator=None):
         self._h = handle
         self.n = n
         self.nsets = nsets
         self.offsets = offsets
+        self._allocator = allocator  # kept alive while the tree may call it
 
     @property
     def handle(self):
@@ -246,6 +325,38 @@ class Tree:
             _check(lib.jz_forest_fof(self.handle, bb.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
                                      ctypes.c_void_p(label.data_ptr()), _stream(stream)))
         return label
+
+    def size(self) -> int:
+        """Device bytes the tree holds between calls (jz_tree_size)."""
+        return int(lib.jz_tree_size(self.handle))
+
+    def catalogue(self, b: float, min_members: int = 20, vel=None, max_groups=None,
+                  stream=None):
+        """FoF catalogue (jz_fof_catalogue): dict with ``label`` and ``order``
+        (device int32 [n]) and ``groups`` (host structured array, GROUP_DTYPE)."""
+        import torch
+        dev = torch.device("cuda", torch.cuda.current_device())
+        label = torch.empty(self.n, dtype=torch.int32, device=dev)
+        order = torch.empty(self.n, dtype=torch.int32, device=dev)
+        if max_groups is None:
+            max_groups = self.n // max(1, int(min_members)) + 1
+        gbuf = torch.empty(max(1, int(max_groups)) * GROUP_DTYPE.itemsize, dtype=torch.uint8,
+                           device=dev)
+        vp = None
+        if vel is not None:
+            if not isinstance(vel, torch.Tensor) or not vel.is_cuda or vel.dtype != torch.float32 \
+                    or tuple(vel.shape) != (self.n, 3):
+                raise TypeError("vel must be a CUDA float32 tensor of shape (n, 3)")
+            vel = vel.contiguous()
+            vp = ctypes.c_void_p(vel.data_ptr())
+        ng = ctypes.c_int64()
+        _check(lib.jz_fof_catalogue(self.handle, float(np.float32(b)), int(min_members), vp,
+                                    ctypes.c_void_p(label.data_ptr()),
+                                    ctypes.c_void_p(order.data_ptr()),
+                                    ctypes.c_void_p(gbuf.data_ptr()), int(max_groups),
+                                    ctypes.byref(ng), _stream(stream)))
+        g = gbuf[:ng.value * GROUP_DTYPE.itemsize].cpu().numpy().view(GROUP_DTYPE)
+        return {"label": label, "order": order, "groups": g}
 
     def stats(self) -> dict:
         s = Stats()
@@ -292,25 +403,30 @@ class Tree:
             pass
 
 
-def jz_build(points, opts: BuildOpts | None = None, stream=None) -> Tree:
-    """Sort and build the tree for a CUDA float32 (n, 3) tensor."""
+def jz_build(points, opts: BuildOpts | None = None, stream=None, allocator=None) -> Tree:
+    """Sort and build the tree for a CUDA float32 (n, 3) tensor. ``allocator``:
+    None (the library's caching pool), "torch" (torch's caching allocator) or
+    an allocator object (see :class:`TorchAllocator`)."""
     p = _points(points)
     h = ctypes.c_void_p()
+    aref, keep = _alloc_arg(allocator)
     _check(lib.jz_build(ctypes.c_void_p(p.data_ptr()), p.shape[0], _stream(stream),
-                        ctypes.byref(opts) if opts is not None else None, None, ctypes.byref(h)))
-    return Tree(h, p.shape[0])
+                        ctypes.byref(opts) if opts is not None else None, aref, ctypes.byref(h)))
+    return Tree(h, p.shape[0], allocator=keep)
 
 
-def jz_forest_build(points, offsets, opts: BuildOpts | None = None, stream=None) -> Tree:
+def jz_forest_build(points, offsets, opts: BuildOpts | None = None, stream=None,
+                    allocator=None) -> Tree:
     """One tree over many independent sets; ``offsets`` is a host int array [B+1]."""
     p = _points(points)
     off = np.ascontiguousarray(offsets, dtype=np.int64)
     h = ctypes.c_void_p()
+    aref, keep = _alloc_arg(allocator)
     _check(lib.jz_forest_build(ctypes.c_void_p(p.data_ptr()),
                                off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), len(off) - 1,
                                _stream(stream), ctypes.byref(opts) if opts is not None else None,
-                               None, ctypes.byref(h)))
-    return Tree(h, p.shape[0], len(off) - 1, off)
+                               aref, ctypes.byref(h)))
+    return Tree(h, p.shape[0], len(off) - 1, off, allocator=keep)
 
 
 def jz_knn(tree: Tree, k: int, stream=None):
@@ -397,7 +513,9 @@ class Server:
         self._keep[t.value] = keep
         return t.value
 
-    def submit_knn(self, points, k: int, idx=None, dist2=None) -> int:
+    def submit_knn(self, points, k: int, idx=None, dist2=None, stream=None) -> int:
+        """Queue kNN on ``points``; the request waits for the work queued on
+        ``stream`` (default: the current stream) before it reads them."""
         import torch
         p = _points(points)
         n = p.shape[0]
@@ -405,17 +523,19 @@ class Server:
             idx = torch.empty((n, k), dtype=torch.int32, device=p.device)
         if dist2 is None:
             dist2 = torch.empty((n, k), dtype=torch.float32, device=p.device)
-        r = Request(JZ_OP_KNN, int(k), 0.0, p.data_ptr(), n, idx.data_ptr(), dist2.data_ptr(), None)
+        r = Request(JZ_OP_KNN, int(k), 0.0, p.data_ptr(), n, idx.data_ptr(), dist2.data_ptr(), None,
+                    _stream(stream))
         return self._submit(r, (p, idx, dist2))
 
-    def submit_fof(self, points, b: float, label=None) -> int:
+    def submit_fof(self, points, b: float, label=None, stream=None) -> int:
+        """Queue FoF on ``points`` (ordered after ``stream`` as submit_knn)."""
         import torch
         p = _points(points)
         n = p.shape[0]
         if label is None:
             label = torch.empty(n, dtype=torch.int32, device=p.device)
         r = Request(JZ_OP_FOF, 0, float(np.float32(b)), p.data_ptr(), n, None, None,
-                    label.data_ptr())
+                    label.data_ptr(), _stream(stream))
         return self._submit(r, (p, label))
 
     def poll(self, ticket: int):

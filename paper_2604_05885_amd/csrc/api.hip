@@ -335,7 +335,7 @@ jz_status jz_knn(jz_tree *t, int k, int32_t *idx, float *dist2, void *stream) {
     g_err.clear();
     if (!t) return jz_fail(JZ_E_INVALID, "tree is NULL");
     if (k < 1) return jz_fail(JZ_E_INVALID, "k must be >= 1");
-    if (k > 32) return jz_fail(JZ_E_UNSUPPORTED, "k > 32 is not supported");
+    if (k > JZ_MAX_K) return jz_fail(JZ_E_UNSUPPORTED, "k > %d is not supported", JZ_MAX_K);
     if (t->n > 0 && (!idx || !dist2)) return jz_fail(JZ_E_INVALID, "output is NULL");
     DeviceGuard g(t->ac.device);
     return run_knn(t, k, idx, dist2, (hipStream_t)stream);
@@ -370,6 +370,16 @@ void jz_tree_free(jz_tree *t) {
     if (!t) return;
     DeviceGuard g(t->ac.device);
     delete t;
+}
+
+int64_t jz_tree_size(const jz_tree *t) {
+    if (!t) return 0;
+    size_t b = t->d_set_off.bytes + t->pts4.bytes + t->keys.bytes + t->leaf_base.bytes +
+               t->super_spl.bytes + t->knn_top_seg.bytes + t->knn_top_list.bytes +
+               t->fof_top_seg.bytes + t->fof_top_list.bytes;
+    for (int p = 0; p < JZ_MAX_PLANES; ++p)
+        b += t->nodes[p].bytes + t->spl[p].bytes + t->node_set[p].bytes;
+    return (int64_t)b;
 }
 
 jz_status jz_tree_stats(const jz_tree *t, jz_stats *s) {
@@ -416,6 +426,6 @@ void jz_release_cached(void) {
 
 const char *jz_last_error(void) { return g_err.c_str(); }
 
-int jz_abi_version(void) { return 2; }
+int jz_abi_version(void) { return 3; }
 
 }  // extern "C"

@@ -279,6 +279,22 @@ __global__ __launch_bounds__(RS_THREADS) void k_onesweep(
     }
 }
 
+// digit histograms of npass 8-bit passes over n 64-bit keys
+__global__ __launch_bounds__(256) void k_digit_hist(const uint64_t *__restrict__ keys, int64_t n,
+                                                    int npass, uint32_t *__restrict__ hist) {
+    __shared__ uint32_t s_h[kMaxPass * 256];
+    for (int i = threadIdx.x; i < npass * 256; i += blockDim.x) s_h[i] = 0;
+    __syncthreads();
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint64_t key = keys[i];
+        for (int p = 0; p < npass; ++p) atomicAdd(&s_h[p * 256 + ((key >> (8 * p)) & 255u)], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < npass * 256; i += blockDim.x)
+        if (s_h[i]) atomicAdd(hist + i, s_h[i]);
+}
+
 __global__ __launch_bounds__(256) void k_gather(const float *__restrict__ pts,
                                                 const uint32_t *__restrict__ order, int64_t n,
                                                 float4 *__restrict__ out) {
@@ -600,6 +616,50 @@ __global__ void k_node_sets(const Node *__restrict__ nodes, int64_t L,
 
 // ---------------------------------------------------------------------------
 
+// The onesweep passes over the low 8 * npass key bits, with the exclusive
+// digit offsets in doff; (kin, vin) -> sorted pairs, swapping with
+// (kout, vout) after every pass (the result is where the last pass wrote).
+static jz_status onesweep_passes(const AllocCtx *ac, uint64_t *&kin, uint32_t *&vin,
+                                 uint64_t *&kout, uint32_t *&vout, int64_t n, int npass,
+                                 const uint32_t *doff, hipStream_t s) {
+    const int64_t ntiles = (n + RS_TILE - 1) / RS_TILE;
+    DBuf d_status;
+    const size_t per_pass = (size_t)ntiles * 256;
+    JZ_TRY(d_status.get(ac, (per_pass * npass) * sizeof(uint64_t) + 64 * sizeof(int), s));
+    JZ_TRY(zero_words(d_status.as<unsigned long long>(), d_status.bytes / 8, s));
+    int *ctrs = reinterpret_cast<int *>(d_status.as<uint64_t>() + per_pass * npass);
+    for (int p = 0; p < npass; ++p) {
+        k_onesweep<<<(unsigned)ntiles, RS_THREADS, 0, s>>>(
+            kin, vin, kout, vout, n, 8 * p, doff + 256 * p, d_status.as<uint64_t>() + per_pass * p,
+            ctrs + p);
+        std::swap(kin, kout);
+        std::swap(vin, vout);
+    }
+    JZ_HIP(hipGetLastError());
+    return JZ_OK;
+}
+
+jz_status radix_sort_pairs(const AllocCtx *ac, DBuf &k0, DBuf &v0, DBuf &k1, DBuf &v1, int64_t n,
+                           int bits, hipStream_t s) {
+    if (n <= 1 || bits <= 0) return JZ_OK;
+    const int npass = std::min(kMaxPass, (bits + 7) / 8);
+    DBuf d_hist, d_doff;
+    JZ_TRY(d_hist.get(ac, kMaxPass * 256 * sizeof(uint32_t), s));
+    JZ_TRY(d_doff.get(ac, kMaxPass * 256 * sizeof(uint32_t), s));
+    JZ_TRY(zero_words(d_hist.as<unsigned long long>(), d_hist.bytes / 8, s));
+    k_digit_hist<<<std::min<unsigned>(blocks_for(n, 256 * 8), 2048), 256, 0, s>>>(
+        k0.as<uint64_t>(), n, npass, d_hist.as<uint32_t>());
+    k_hist_scan<<<npass, 256, 0, s>>>(d_hist.as<uint32_t>(), d_doff.as<uint32_t>());
+    uint64_t *kin = k0.as<uint64_t>(), *kout = k1.as<uint64_t>();
+    uint32_t *vin = v0.as<uint32_t>(), *vout = v1.as<uint32_t>();
+    JZ_TRY(onesweep_passes(ac, kin, vin, kout, vout, n, npass, d_doff.as<uint32_t>(), s));
+    if (kin != k0.as<uint64_t>()) {
+        std::swap(k0.p, k1.p);
+        std::swap(v0.p, v1.p);
+    }
+    return JZ_OK;
+}
+
 static int plan_planes(int64_t n, const jz_build_opts &o) {
     int P = 1;
     double nmax = (double)o.leaf_max;
@@ -638,8 +698,8 @@ jz_status build_tree(jz_tree *t, const float *points, hipStream_t s) {
     {
         const int init[8] = {INT_MAX, INT_MAX, INT_MAX, INT_MIN, INT_MIN, INT_MIN, 0, 0};
         JZ_HIP(hipMemcpyAsync(d_bbox.p, init, sizeof(init), hipMemcpyHostToDevice, s));
-        JZ_HIP(hipMemsetAsync(d_hist.p, 0, d_hist.bytes, s));
     }
+    JZ_TRY(zero_words(d_hist.as<unsigned long long>(), d_hist.bytes / 8, s));
     const unsigned gb = std::min<unsigned>(blocks_for(n, 256), 1024);
     k_bbox<<<gb, 256, 0, s>>>(points, n, d_bbox.as<int>());
     k_morton<<<std::min<unsigned>(blocks_for(n, 256 * 8), 2048), 256, 0, s>>>(
@@ -650,22 +710,9 @@ jz_status build_tree(jz_tree *t, const float *points, hipStream_t s) {
 
     // 3: radix sort
     {
-        const int64_t ntiles = (n + RS_TILE - 1) / RS_TILE;
-        DBuf d_status;
-        const size_t per_pass = (size_t)ntiles * 256;
-        JZ_TRY(d_status.get(ac, (per_pass * npass) * sizeof(uint64_t) + 64 * sizeof(int), s));
-        JZ_HIP(hipMemsetAsync(d_status.p, 0, d_status.bytes, s));
-        int *ctrs = reinterpret_cast<int *>(d_status.as<uint64_t>() + per_pass * npass);
         uint64_t *kin = k0.as<uint64_t>(), *kout = k1.as<uint64_t>();
         uint32_t *vin = v0.as<uint32_t>(), *vout = v1.as<uint32_t>();
-        for (int p = 0; p < npass; ++p) {
-            k_onesweep<<<(unsigned)ntiles, RS_THREADS, 0, s>>>(
-                kin, vin, kout, vout, n, 8 * p, d_doff.as<uint32_t>() + 256 * p,
-                d_status.as<uint64_t>() + per_pass * p, ctrs + p);
-            std::swap(kin, kout);
-            std::swap(vin, vout);
-        }
-        JZ_HIP(hipGetLastError());
+        JZ_TRY(onesweep_passes(ac, kin, vin, kout, vout, n, npass, d_doff.as<uint32_t>(), s));
         // sorted data is in (kin, vin)
         if (kin != k0.as<uint64_t>()) {
             std::swap(k0.p, k1.p);

@@ -276,7 +276,7 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_fof(
                 const bool real = lane < cnt;
                 float4 p = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
                 if (real) p = pts[st + lane];
-                if (lane < size) tile[o_r[q] + lane] = p;
+                if (lane < size) tile[tslot(o_r[q] + lane)] = p;
                 const float lx = group8_min(real ? p.x : INFINITY);
                 const float ly = group8_min(real ? p.y : INFINITY);
                 const float lz = group8_min(real ? p.z : INFINITY);
@@ -284,45 +284,69 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_fof(
                 const float hy = group8_max(real ? p.y : -INFINITY);
                 const float hz = group8_max(real ? p.z : -INFINITY);
                 if ((lane & 7) == 0 && lane < size) {
+                    // the chunk's box; lo.w: its number of real points, hi.w:
+                    // the z-index of its first position
                     float4 *bx = cbox + ((o_r[q] + lane) >> 3) * 2;
-                    bx[0] = make_float4(lx, ly, lz, 0.0f);
-                    bx[1] = make_float4(hx, hy, hz, 0.0f);
+                    bx[0] = make_float4(lx, ly, lz, __int_as_float(min(8, max(0, cnt - lane))));
+                    bx[1] = make_float4(hx, hy, hz, __int_as_float(st + lane));
                 }
             }
         }
         wave_lds_sync();
+        // 1: which tile positions link to this lane's point (a point links to
+        // the later points of a pair only). Every lane marks the chunks its
+        // point can reach (chunk box within b; a chunk box lies inside its
+        // source's box) and pops its own chunks, so a pass costs the largest
+        // per-lane chunk count, not the number of chunks any lane needs.
+        const int nch = uni(npts >> 3);
+        unsigned M = 0;
+        for (int c = 0; c < nch; ++c) {
+            const float4 *bx = cbox + c * 2;
+            const float4 blo = bx[0], bhi = bx[1];
+            const float gx = fmaxf(fmaxf(blo.x - me.x, me.x - bhi.x), 0.0f);
+            const float gy = fmaxf(fmaxf(blo.y - me.y, me.y - bhi.y), 0.0f);
+            const float gz = fmaxf(fmaxf(blo.z - me.z, me.z - bhi.z), 0.0f);
+            const float xx = gx * gx;
+            const float yy = gy * gy;
+            const float zz = gz * gz;
+            const float sxy = xx + yy;
+            M |= (act && sxy + zz <= bb) ? (1u << c) : 0u;
+        }
+        uint64_t lk[FTILE / 64] = {};
+        const int nit = uni(wave_max_i(__popc(M)));
+        for (int it = 0; it < nit; ++it) {
+            const bool has = M != 0u;
+            const int c = has ? __ffs((int)M) - 1 : 0;
+            M &= M - 1u;
+            const int real = has ? __float_as_int(cbox[c * 2].w) : 0;
+            const int cfirst = __float_as_int(cbox[c * 2 + 1].w);
+            unsigned m8 = 0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const float4 s = tile[tslot(c * 8 + u)];
+                const float dd = dist2_pts(me.x, me.y, me.z, s.x, s.y, s.z);
+                m8 |= (u < real && cfirst + u > my && dd <= bb) ? (1u << u) : 0u;
+            }
+#pragma unroll
+            for (int h = 0; h < FTILE / 64; ++h)
+                lk[h] |= (c >> 3) == h ? (uint64_t)m8 << ((c & 7) * 8) : 0ull;
+            evals += (unsigned)real;
+        }
         for (int q = 0; q < take; ++q) {
             if (!((any >> q) & 1u)) continue;
-            const bool need = (needbits >> q) & 1u;
             const bool wB = (wholemask >> q) & 1u;
             const int f0 = uni(offs[q]), f1 = uni(offs[q + 1]);
             const int b0 = uni(nb[q].start), cnt = uni(nb[q].count);
-            // 1: which points of this source link to this lane's point (a
-            // point links to the later points of the pair only)
+            // this source's positions [f0, f1) of the tile link mask (f0 is a
+            // multiple of 8 and a source spans at most 64 positions)
+            const int h0 = f0 >> 6, sh = f0 & 63;
             uint64_t lm = 0;
-            for (int j0 = f0; j0 < f1; j0 += 8) {
-                const float4 *bx = cbox + (j0 >> 3) * 2;
-                const float4 blo = bx[0], bhi = bx[1];
-                const float gx = fmaxf(fmaxf(blo.x - me.x, me.x - bhi.x), 0.0f);
-                const float gy = fmaxf(fmaxf(blo.y - me.y, me.y - bhi.y), 0.0f);
-                const float gz = fmaxf(fmaxf(blo.z - me.z, me.z - bhi.z), 0.0f);
-                const float xx = gx * gx;
-                const float yy = gy * gy;
-                const float zz = gz * gz;
-                const float sxy = xx + yy;
-                const bool cneed = need && sxy + zz <= bb;
-                if (!__ballot(cneed)) continue;
-                const int first = b0 + (j0 - f0);  // point index of position j0
-                unsigned m8 = 0;
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const float4 s = tile[j0 + u];
-                    const float dd = dist2_pts(me.x, me.y, me.z, s.x, s.y, s.z);
-                    m8 |= (cneed && first + u > my && dd <= bb) ? (1u << u) : 0u;
-                }
-                lm |= (uint64_t)m8 << (j0 - f0);
-                if (cneed) evals += (unsigned)min(8, cnt - (j0 - f0));
+            for (int h = 0; h < FTILE / 64; ++h) {
+                if (h == h0) lm |= lk[h] >> sh;
+                if (h == h0 + 1 && sh) lm |= lk[h] << (64 - sh);
             }
+            if (f1 - f0 < 64) lm &= (1ull << (f1 - f0)) - 1ull;
             const uint64_t linking = __ballot(lm != 0);
             if (!linking) continue;
             if (wA && wB) {
@@ -363,14 +387,16 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_fof(
 
 // Root of every point (a read-only find: no other thread writes uf[i] now)
 // and the smallest input index per root. Points of one group are mostly
-// contiguous in z-order, so the lanes of a wave first combine their values per
-// root and one lane per distinct root issues the atomic.
+// contiguous in z-order: the wave takes the minimum over each run of lanes
+// with the same root (a segmented scan, 6 steps whatever the number of runs)
+// and the last lane of a run issues one atomic for it.
 __global__ __launch_bounds__(256) void k_flatten_min(int *__restrict__ uf,
                                                      const float4 *__restrict__ pts, int64_t n,
                                                      int *__restrict__ minidx) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = i < n;
-    int root = 0, v = INT_MAX;
+    const int lane = lane_id();
+    int root = -1 - lane, v = INT_MAX;  // invalid lanes: a root of their own
     if (valid) {
         int x = (int)i;
         int p = ld_acq(uf + x);
@@ -382,16 +408,19 @@ __global__ __launch_bounds__(256) void k_flatten_min(int *__restrict__ uf,
         uf[i] = x;
         v = __float_as_int(pts[i].w);
     }
-    uint64_t pending = __ballot(valid);
-    while (pending) {
-        const int leader = __ffsll((unsigned long long)pending) - 1;
-        const int r0 = __builtin_amdgcn_readlane(root, leader);
-        const bool mine = valid && root == r0;
-        const uint64_t m = __ballot(mine);
-        const int vm = wave_min_i(mine ? v : INT_MAX);
-        if (lane_id() == leader) atomicMin(minidx + r0, vm);
-        pending &= ~m;
+    // segmented inclusive min-scan over runs of equal roots
+    const int prev_root = __shfl_up(root, 1, 64);
+    bool head = lane == 0 || prev_root != root;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int vu = __shfl_up(v, o, 64);
+        const bool hu = __shfl_up((int)head, o, 64) != 0;
+        if (lane >= o && !head) v = min(v, vu);
+        if (lane >= o) head = head || hu;
     }
+    const int next_root = __shfl_down(root, 1, 64);
+    const bool tail = lane == 63 || next_root != root;
+    if (valid && tail) atomicMin(minidx + root, v);
 }
 
 __global__ void k_labels(const int *__restrict__ uf, const float4 *__restrict__ pts, int64_t n,
@@ -425,6 +454,7 @@ jz_status run_fof(jz_tree *t, const float *b2_set_host, int32_t *label, hipStrea
     t->st.reruns = 0;
     t->st.insert_rounds = t->st.tile_steps = 0;
     t->st.lists_sorted_long = t->st.lists_unordered = 0;
+    for (int p = 0; p <= JZ_MAX_PLANES; ++p) t->st.lists_presorted[p][0] = t->st.lists_presorted[p][1] = 0;
     if (n == 0) return JZ_OK;
 
     const bool sets = t->nsets > 1;

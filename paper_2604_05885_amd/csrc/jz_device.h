@@ -57,6 +57,13 @@ __device__ __forceinline__ float box_up2(const Node &a, const Node &b) {
     return s + zz;
 }
 
+// LDS slot of position j of a staged point tile (float4 per point): inside
+// each chunk of 8 positions the slots are permuted by the chunk's low 3 bits,
+// so that lanes reading the same position of different chunks at once spread
+// over the LDS banks (unpermuted, every chunk starts at a multiple of 128
+// bytes and all of them meet in one bank group).
+__device__ __forceinline__ int tslot(int j) { return j ^ ((j >> 3) & 7); }
+
 // ---------------------------------------------------------------------------
 // wave64 primitives
 

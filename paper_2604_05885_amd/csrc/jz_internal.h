@@ -131,10 +131,23 @@ jz_status tree_create(const float *points, const int64_t *offsets, int nsets, hi
 
 // pipelines (build.hip / knn.hip / fof.hip)
 jz_status build_tree(jz_tree *t, const float *points, hipStream_t s);
-jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s);
+// run_knn takes its per-call scratch from `scratch` when given (instead of
+// the tree's allocator); every buffer it acquires after its fixed ones is a
+// level list, acquired top level first and released bottom level first.
+jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s,
+                  const AllocCtx *scratch = nullptr);
 jz_status run_fof(jz_tree *t, const float *b2_set_host, int32_t *label, hipStream_t s);
 
 bool jz_profiling();
+
+// fill n 64-bit words with zero on stream s (a kernel, not a memset node)
+jz_status zero_words(unsigned long long *p, size_t n, hipStream_t s);
+
+// Stable LSD radix sort (8-bit digits) of n (key, value) pairs on the low
+// `bits` key bits: k0 / v0 hold the input and, on return, the sorted pairs
+// (the DBufs may have traded pointers with the scratch pair k1 / v1).
+jz_status radix_sort_pairs(const AllocCtx *ac, DBuf &k0, DBuf &v0, DBuf &k1, DBuf &v1, int64_t n,
+                           int bits, hipStream_t s);
 
 // Process-wide memory of interaction-list sizes: the largest entries-per-node
 // ratio seen for (operation, k, level), so that later calls on similar data

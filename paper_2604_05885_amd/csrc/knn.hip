@@ -562,6 +562,7 @@ constexpr int TILE_PTS = 256; // source points staged per batch (positions fit a
 constexpr int CQ = 32;        // queued candidate positions per lane
 constexpr int CH = 8;         // tile positions a lane scans between queue checks
 
+
 // Keep the K smallest of two ascending key lists a and b in a (ascending).
 // With both lists padded to M = next power of two, min(a[i], b[M-1-i]) is a
 // bitonic sequence holding the M smallest of the padded union (so the K
@@ -672,13 +673,20 @@ __device__ __forceinline__ void merge_chunk(TopK<K> &a, const double (&ch)[C]) {
 // Candidates within the k-th distance are queued as tile positions and
 // inserted into the register top-k in rounds, so insert time follows the
 // busiest lane rather than every accepted candidate of any lane.
-template <int K>
+//
+// k > 32 takes several passes (the paper's LeafToLeaf with at most 32
+// neighbours per call, called again for the next ones): a pass with LO finds
+// the K smallest keys strictly above the last key of the previous pass (read
+// back from column col0 - 1 of the output row), so that equal distances
+// continue by index. A pass writes columns [col0, col0 + kw) of rows of
+// out_stride entries.
+template <int K, bool LO>
 __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
     const int2 *__restrict__ seg, int2 *__restrict__ list, const Node *__restrict__ leaves,
     const float4 *__restrict__ pts, int n_leaves, const int *__restrict__ leaf_base,
     int32_t *__restrict__ out_idx, float *__restrict__ out_d2,
     unsigned long long *__restrict__ stats, const unsigned long long *__restrict__ overflow,
-    int sort_cap, int presorted) {
+    int sort_cap, int presorted, int out_stride, int col0, int kw) {
     // one block per wave: the staged list (LCAP entries), the point tile,
     // the (lo, hi) box of every 8 tile positions and the candidate queues;
     // before the walk the whole block is the scratch in which a longer list
@@ -695,10 +703,22 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
     const Node a = leaves[A];
     const int acount = uni(a.count);
     const int lgS = acount <= 16 ? 2 : (acount <= 32 ? 1 : 0);  // log2 lanes per query
-    const int S = 1 << lgS;
     const int q = lane & ((64 >> lgS) - 1), h = lane >> (6 - lgS);
     const bool act = q < acount;
     const float4 me = pts[a.start + (act ? q : 0)];
+    const int64_t row = (int64_t)__float_as_int(me.w);
+    const int base = leaf_base ? leaf_base[A] : 0;
+    // keys at or below lo (and distances below lo_d) belong to earlier passes
+    double lo = -1.0;
+    float lo_d = 0.0f;
+    if constexpr (LO) {
+        if (act) {
+            const int pi = out_idx[row * out_stride + col0 - 1];
+            const float pd = out_d2[row * out_stride + col0 - 1];
+            lo = pi < 0 ? __builtin_bit_cast(double, PAD_KEY) : key_of(pd, pi + base);
+            lo_d = pi < 0 ? INFINITY : pd;
+        }
+    }
     const int2 sg = seg[A];
     int2 *gl = list + uni(sg.x);
     const int len = uni(sg.y);
@@ -745,7 +765,8 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
                 const int qv = q0[64 * slot];
                 const float4 s = tile[c + u < qn ? qv : 0];
                 const float dd = dist2_pts(me.x, me.y, me.z, s.x, s.y, s.z);
-                ch[u] = c + u < qn ? key_of(dd, __float_as_int(s.w)) : pad;
+                const double kk = key_of(dd, __float_as_int(s.w));
+                ch[u] = (c + u < qn && (!LO || kk > lo)) ? kk : pad;
             }
             sort_keys<8>(ch);
             merge_chunk<K, 8>(best, ch);
@@ -823,7 +844,7 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
                 const bool real = lane < cnt;
                 float4 p = make_float4(INFINITY, INFINITY, INFINITY, __int_as_float(-1));
                 if (real) p = pts[st + lane];
-                if (lane < size) tile[o_r[qq] + lane] = p;
+                if (lane < size) tile[tslot(o_r[qq] + lane)] = p;
                 float lx = real ? p.x : INFINITY, ly = real ? p.y : INFINITY,
                       lz = real ? p.z : INFINITY;
                 float hx = real ? p.x : -INFINITY, hy = real ? p.y : -INFINITY,
@@ -835,8 +856,9 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
                 hy = group8_max(hy);
                 hz = group8_max(hz);
                 if ((lane & 7) == 0 && lane < size) {
+                    // the chunk's box, and in lo.w its number of real points
                     float4 *bx = cbox + ((o_r[qq] + lane) >> 3) * 2;
-                    bx[0] = make_float4(lx, ly, lz, 0.0f);
+                    bx[0] = make_float4(lx, ly, lz, __int_as_float(min(8, max(0, cnt - lane))));
                     bx[1] = make_float4(hx, hy, hz, 0.0f);
                 }
             }
@@ -860,9 +882,10 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
 #pragma unroll
                         for (int u = 0; u < C; ++u) {
                             if (j0 + u * SS < f1) {
-                                const float4 p = tile[j0 + u * SS + h];
+                                const float4 p = tile[tslot(j0 + u * SS + h)];
                                 const float dd = dist2_pts(me.x, me.y, me.z, p.x, p.y, p.z);
-                                ch[u] = key_of(dd, __float_as_int(p.w));
+                                const double kk = key_of(dd, __float_as_int(p.w));
+                                ch[u] = (!LO || kk > lo) ? kk : pad;
                             } else {
                                 ch[u] = pad;
                             }
@@ -876,46 +899,53 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
                 }
                 return;
             }
-            for (int qq = 0; qq < take; ++qq) {
-                if (!((any >> qq) & 1u)) continue;
-                ++visited;
-                const bool need = (needbits >> qq) & 1u;
-                const int f0 = uni(offs[qq]), f1 = uni(offs[qq + 1]);
-                const int cnt = uni(nb[qq].count);
-                for (int j0 = f0; j0 < f1; j0 += 8) {
-                    // 8 positions with their box: skipped when no lane's query
-                    // can reach the box; a lane that cannot accepts nothing
-                    const float4 *bx = cbox + (j0 >> 3) * 2;
-                    const float4 blo = bx[0], bhi = bx[1];
-                    const float gx = fmaxf(fmaxf(blo.x - me.x, me.x - bhi.x), 0.0f);
-                    const float gy = fmaxf(fmaxf(blo.y - me.y, me.y - bhi.y), 0.0f);
-                    const float gz = fmaxf(fmaxf(blo.z - me.z, me.z - bhi.z), 0.0f);
-                    const float xx = gx * gx;
-                    const float yy = gy * gy;
-                    const float zz = gz * gz;
-                    const float sxy = xx + yy;
-                    const bool cneed = need && sxy + zz <= kth;
-                    if (!__ballot(cneed)) continue;
-                    const float thr = cneed ? kth : -1.0f;
-#pragma unroll 4
-                    for (int u = 0; u < 8 / SS; ++u) {
-                        const int j = j0 + u * SS + h;
-                        const float4 p = tile[j];
-                        const float dd = dist2_pts(me.x, me.y, me.z, p.x, p.y, p.z);
-                        // written always, kept only if accepted (at most CH
-                        // steps from qn <= CQ - CH, so the slot exists)
-                        *qp = (uint8_t)j;
-                        qp += dd <= thr ? 64 : 0;
-                    }
-                    steps += (unsigned)(8 / SS);
-                    if (cneed) {
-                        const int r = min(8, cnt - (j0 - f0));
-                        evals += r > h ? (unsigned)((r - h + SS - 1) / SS) : 0u;
-                    }
-                    if (__ballot(qp > qlim)) {
-                        drain();
-                        kth = group_kth();
-                    }
+            // Every lane marks the 8-position chunks of the tile its query can
+            // reach (chunk box within the group's k-th distance; a chunk box
+            // lies inside its source's box, so this also drops the sources the
+            // query does not need), then pops its own chunks, lowest first:
+            // the lanes work on different chunks at once, so a pass costs the
+            // largest per-lane chunk count instead of the number of chunks any
+            // lane needs. The S lanes of a query share kth and so the mask,
+            // and split each chunk's positions.
+            visited += (unsigned)__popc(any & ((1u << take) - 1u));
+            const int nch = uni(npts >> 3);
+            unsigned M = 0;
+            for (int c = 0; c < nch; ++c) {
+                const float4 *bx = cbox + c * 2;
+                const float4 blo = bx[0], bhi = bx[1];
+                const float gx = fmaxf(fmaxf(blo.x - me.x, me.x - bhi.x), 0.0f);
+                const float gy = fmaxf(fmaxf(blo.y - me.y, me.y - bhi.y), 0.0f);
+                const float gz = fmaxf(fmaxf(blo.z - me.z, me.z - bhi.z), 0.0f);
+                const float xx = gx * gx;
+                const float yy = gy * gy;
+                const float zz = gz * gz;
+                const float sxy = xx + yy;
+                M |= (act && sxy + zz <= kth) ? (1u << c) : 0u;
+            }
+            const int nit = uni(wave_max_i(__popc(M)));
+            for (int it = 0; it < nit; ++it) {
+                const bool has = M != 0u;
+                const int c = has ? __ffs((int)M) - 1 : 0;
+                M &= M - 1u;
+                const float thr = has ? kth : -1.0f;
+#pragma unroll
+                for (int u = 0; u < 8 / SS; ++u) {
+                    const int j = tslot(c * 8 + u * SS + h);
+                    const float4 p = tile[j];
+                    const float dd = dist2_pts(me.x, me.y, me.z, p.x, p.y, p.z);
+                    // written always, kept only if accepted (at most CH
+                    // positions per pop from qn <= CQ - CH: the slot exists)
+                    *qp = (uint8_t)j;
+                    qp += (dd <= thr && (!LO || dd >= lo_d)) ? 64 : 0;
+                }
+                steps += (unsigned)(8 / SS);
+                if (has) {
+                    const int r = __float_as_int(cbox[c * 2].w);
+                    evals += r > h ? (unsigned)((r - h + SS - 1) / SS) : 0u;
+                }
+                if (__ballot(qp > qlim)) {
+                    drain();
+                    kth = group_kth();
                 }
             }
         };
@@ -940,16 +970,16 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
         merge_topk<K>(best, other);
     }
     if (act && h == 0) {
-        const int64_t row = (int64_t)__float_as_int(me.w);
-        const int base = leaf_base ? leaf_base[A] : 0;
-        int32_t *oi = out_idx + row * K;
-        float *od = out_d2 + row * K;
+        int32_t *oi = out_idx + row * out_stride + col0;
+        float *od = out_d2 + row * out_stride + col0;
 #pragma unroll
         for (int r = 0; r < K; ++r) {
-            const uint64_t e = bits_of(best.get(r));
-            const bool none = e == PAD_KEY;
-            oi[r] = none ? -1 : (int)(uint32_t)e - base;
-            od[r] = none ? INFINITY : __uint_as_float((uint32_t)(e >> 32));
+            if (r < kw) {
+                const uint64_t e = bits_of(best.get(r));
+                const bool none = e == PAD_KEY;
+                oi[r] = none ? -1 : (int)(uint32_t)e - base;
+                od[r] = none ? INFINITY : __uint_as_float((uint32_t)(e >> 32));
+            }
         }
     }
     const int ev = wave_sum_i((int)evals);
@@ -965,13 +995,15 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
 
 typedef void (*leaf_fn)(const int2 *, int2 *, const Node *, const float4 *, int, const int *,
                         int32_t *, float *, unsigned long long *, const unsigned long long *, int,
-                        int);
+                        int, int, int, int);
 
 template <int K>
 leaf_fn leaf_ptr() {
-    return k_leaf_knn<K>;
+    return k_leaf_knn<K, false>;
 }
 
+// the leaf kernel of a first pass with K = k (k <= 32); later passes of a
+// k > 32 search use k_leaf_knn<32, true>
 leaf_fn leaf_kernel(int k) {
     static const leaf_fn table[33] = {
         nullptr,       leaf_ptr<1>(),  leaf_ptr<2>(),  leaf_ptr<3>(),  leaf_ptr<4>(),
@@ -986,8 +1018,24 @@ leaf_fn leaf_kernel(int k) {
 
 }  // namespace
 
-jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s) {
-    const AllocCtx *ac = &t->ac;
+namespace {
+__global__ __launch_bounds__(256) void k_zero_words(unsigned long long *__restrict__ p, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+}  // namespace
+
+jz_status zero_words(unsigned long long *p, size_t n, hipStream_t s) {
+    if (n == 0) return JZ_OK;
+    k_zero_words<<<(unsigned)std::min<size_t>((n + 255) / 256, 1024), 256, 0, s>>>(p, n);
+    JZ_HIP(hipGetLastError());
+    return JZ_OK;
+}
+
+jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s,
+                  const AllocCtx *scratch) {
+    const AllocCtx *ac = scratch ? scratch : &t->ac;
     const int P = t->P;
     for (int p = 0; p <= JZ_MAX_PLANES; ++p) t->st.list_entries[p] = 0;
     t->st.leaf_pairs = t->st.leaf_pairs_visited = 0;
@@ -996,6 +1044,7 @@ jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s) 
     t->st.reruns = 0;
     t->st.insert_rounds = t->st.tile_steps = 0;
     t->st.lists_sorted_long = t->st.lists_unordered = 0;
+    for (int p = 0; p <= JZ_MAX_PLANES; ++p) t->st.lists_presorted[p][0] = t->st.lists_presorted[p][1] = 0;
     if (t->n == 0) return JZ_OK;
 
     // counters: four leaf statistics (evaluations, sources visited, insert
@@ -1008,7 +1057,7 @@ jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s) 
     const size_t nctr = c_items + JZ_MAX_PLANES;
     JZ_TRY(d_ctr.get(ac, nctr * sizeof(unsigned long long), s));
     unsigned long long *ctr = d_ctr.as<unsigned long long>();
-    JZ_HIP(hipMemsetAsync(ctr, 0, d_ctr.bytes, s));
+    JZ_TRY(zero_words(ctr, nctr, s));
     int64_t cap[JZ_MAX_PLANES];
     DBuf segs[JZ_MAX_PLANES], lists[JZ_MAX_PLANES];
     for (int p = 0; p < P; ++p) {
@@ -1057,6 +1106,11 @@ jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s) 
     // down are rerun with larger lists; the levels above are still valid.
     int start = P - 1;
     for (;;) {
+        // the lists of the levels to (re)run: released bottom level first,
+        // then acquired top level first (a scratch region handed out in
+        // stack order takes them back and reuses the space)
+        for (int p = 0; p <= start; ++p)
+            if (lists[p].bytes < (size_t)cap[p] * sizeof(int2)) lists[p].release();
         for (int p = start; p >= 0; --p) JZ_TRY(lists[p].ensure(ac, cap[p] * sizeof(int2), s));
         if (ev.on) JZ_HIP(hipEventRecord(ev[0], s));
         for (int p = start; p >= 0; --p) {
@@ -1083,11 +1137,18 @@ jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s) 
                 ctr + c_long + 2 * JZ_MAX_PLANES);
         JZ_HIP(hipGetLastError());
         if (ev.on) JZ_HIP(hipEventRecord(ev[1], s));
-        leaf_kernel(k)<<<blocks_for(t->L[0], WPB), 64 * WPB, 0, s>>>(
-            segs[0].as<int2>(), lists[0].as<int2>(), t->nodes[0].as<Node>(), t->pts4.as<float4>(),
-            (int)t->L[0], t->nsets > 1 ? t->leaf_base.as<int>() : nullptr, idx, dist2,
-            ctr + CTR_STATS, ctr + CTR_FLAG, leaf_cap, sort_max);
-        JZ_HIP(hipGetLastError());
+        // k <= 32: one pass; larger k: passes of 32 neighbours, each after
+        // the last key of the one before
+        for (int col = 0; col < k; col += 32) {
+            const leaf_fn fn = k <= 32 ? leaf_kernel(k)
+                                       : (col == 0 ? leaf_kernel(32) : k_leaf_knn<32, true>);
+            fn<<<blocks_for(t->L[0], WPB), 64 * WPB, 0, s>>>(
+                segs[0].as<int2>(), lists[0].as<int2>(), t->nodes[0].as<Node>(),
+                t->pts4.as<float4>(), (int)t->L[0], t->nsets > 1 ? t->leaf_base.as<int>() : nullptr,
+                idx, dist2, ctr + CTR_STATS, ctr + CTR_FLAG, leaf_cap, sort_max, k, col,
+                std::min(32, k - col));
+            JZ_HIP(hipGetLastError());
+        }
         if (ev.on) JZ_HIP(hipEventRecord(ev[2], s));
         std::vector<unsigned long long> hc(nctr);
         JZ_HIP(hipMemcpyAsync(hc.data(), ctr, nctr * sizeof(unsigned long long),
@@ -1114,9 +1175,8 @@ jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s) 
             start = redo;
             // clear the counters of the levels to redo, the flag and the leaf
             // statistics
-            JZ_HIP(hipMemsetAsync(ctr, 0, (size_t)(start + 1) * LIST_ARENAS * sizeof(unsigned long long), s));
-            JZ_HIP(hipMemsetAsync(ctr + CTR_FLAG, 0,
-                                  (nctr - CTR_FLAG) * sizeof(unsigned long long), s));
+            JZ_TRY(zero_words(ctr, (size_t)(start + 1) * LIST_ARENAS, s));
+            JZ_TRY(zero_words(ctr + CTR_FLAG, nctr - CTR_FLAG, s));
             continue;
         }
         for (int p = 0; p < P; ++p) {
@@ -1130,6 +1190,9 @@ jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s) 
         t->st.tile_steps = (int64_t)stat_sum(hc.data(), 3);
         t->st.lists_sorted_long = (int64_t)stat_sum(hc.data(), 4);
         t->st.lists_unordered = (int64_t)stat_sum(hc.data(), 5);
+        for (int p = 0; p <= JZ_MAX_PLANES; ++p)
+            for (int j = 0; j < 2; ++j)
+                t->st.lists_presorted[p][j] = (int64_t)hc[c_long + 2 * p + j];
         if (ev.on) {
             float ms = 0;
             JZ_HIP(hipEventElapsedTime(&ms, ev[1], ev[2]));

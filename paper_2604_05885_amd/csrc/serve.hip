@@ -35,6 +35,7 @@ int64_t steady_ns() {
 struct Req {
     uint64_t ticket = 0;
     jz_request r{};
+    hipEvent_t ready = nullptr;  // recorded on the caller's stream at submission
     size_t bytes = 0;
     bool done = false;
     jz_status status = JZ_OK;
@@ -59,7 +60,7 @@ jz_status check_request(const jz_request *r) {
         return jz_fail(JZ_E_INVALID, "n must be in [0, 2^31-2]");
     if (r->op == JZ_OP_KNN) {
         if (r->k < 1) return jz_fail(JZ_E_INVALID, "k must be >= 1");
-        if (r->k > 32) return jz_fail(JZ_E_UNSUPPORTED, "k > 32 is not supported");
+        if (r->k > JZ_MAX_K) return jz_fail(JZ_E_UNSUPPORTED, "k > %d is not supported", JZ_MAX_K);
         if (r->n > 0 && (!r->idx || !r->dist2)) return jz_fail(JZ_E_INVALID, "kNN outputs are NULL");
     } else if (r->op == JZ_OP_FOF) {
         if (!(r->b >= 0.0f) || !std::isfinite(r->b))
@@ -100,6 +101,10 @@ jz_status run_batch(jz_server *S, const std::vector<Req *> &batch, hipStream_t s
     for (int i = 0; i < nsets; ++i) off[i + 1] = off[i] + batch[i]->r.n;
     const int64_t n = off[nsets];
     const bool single = nsets == 1;
+    // the caller's work on its stream up to each submission (writes of the
+    // points, or the copy that made them contiguous) comes first
+    for (Req *q : batch)
+        if (q->ready) JZ_HIP(hipStreamWaitEvent(s, q->ready, 0));
     // inputs: a single request is used in place, a batch is concatenated
     DBuf pts;
     const float *p = h.points;
@@ -294,8 +299,18 @@ jz_status jz_server_submit(jz_server *S, const jz_request *r, uint64_t *ticket) 
     if (!q) return jz_fail(JZ_E_OOM, "host allocation failed");
     q->r = *r;
     q->bytes = bytes;
+    if (r->n > 0) {
+        hipError_t e = hipEventCreateWithFlags(&q->ready, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(q->ready, (hipStream_t)r->stream);
+        if (e != hipSuccess) {
+            if (q->ready) (void)hipEventDestroy(q->ready);
+            delete q;
+            return jz_hip_fail(e, "recording the submission event", __FILE__, __LINE__);
+        }
+    }
     std::lock_guard<std::mutex> lk(S->m);
     if (S->stop) {
+        if (q->ready) (void)hipEventDestroy(q->ready);
         delete q;
         return jz_fail(JZ_E_INVALID, "server is stopping");
     }
@@ -351,6 +366,7 @@ jz_status jz_server_release(jz_server *S, uint64_t ticket) {
     auto it = S->reqs.find(ticket);
     if (it == S->reqs.end()) return jz_fail(JZ_E_INVALID, "unknown ticket");
     if (!it->second->done) return jz_fail(JZ_E_INVALID, "request is not done");
+    if (it->second->ready) (void)hipEventDestroy(it->second->ready);
     delete it->second;
     S->reqs.erase(it);
     return JZ_OK;
@@ -372,7 +388,10 @@ void jz_server_destroy(jz_server *S) {
     }
     S->cv_work.notify_all();
     for (auto &th : S->workers) th.join();
-    for (auto &kv : S->reqs) delete kv.second;
+    for (auto &kv : S->reqs) {
+        if (kv.second->ready) (void)hipEventDestroy(kv.second->ready);
+        delete kv.second;
+    }
     delete S;
 }
 

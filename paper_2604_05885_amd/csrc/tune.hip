@@ -50,7 +50,7 @@ extern "C" jz_status jz_autotune(const float *points, const int64_t *offsets, in
                                  int k, const float *b, void *stream, const jz_build_opts *base,
                                  jz_build_opts *best, double *best_ms) {
     if (!best) return jz_fail(JZ_E_INVALID, "best is NULL");
-    if (k < 0 || k > 32) return jz_fail(JZ_E_INVALID, "k must be in [0, 32]");
+    if (k < 0 || k > JZ_MAX_K) return jz_fail(JZ_E_INVALID, "k must be in [0, %d]", JZ_MAX_K);
     if (k == 0 && !b) return jz_fail(JZ_E_INVALID, "nothing to tune (k = 0 and b = NULL)");
     std::vector<int64_t> off;
     if (offsets) {

@@ -14,7 +14,7 @@ def test_library_exports_every_header_symbol():
     for name in names:
         assert hasattr(api.lib, name), name
     assert set(names) == set(api._SIGS)  # the binding covers the whole header
-    assert api.lib.jz_abi_version() == 2
+    assert api.lib.jz_abi_version() == 3
 
 
 def test_default_opts():

@@ -2,8 +2,9 @@
 C ABI), in the launch configuration the benchmark uses:
 
 * N = 2^27 clustered (2^16 clumps), kNN k = 32 and FoF at alpha = 0.2:
-  sampled kNN rows against brute force, whole-output invariants on the GPU,
-  and every FoF label against the exact kd-tree oracle;
+  every kNN row against the exact kd-tree oracle, sampled rows against brute
+  force, whole-output invariants on the GPU, and every FoF label against the
+  kd-tree oracle;
 * 4096 ragged clustered sets (N log-uniform in [2^10, 2^18]) solved as one
   forest: every set equal to its standalone solve, sampled sets against the
   oracle;
@@ -70,7 +71,12 @@ def knn_invariants(pts, idx, d2):
         assert torch.equal(ref.view(torch.int32), d2[c:e].view(torch.int32))
 
 
+@pytest.mark.timeout(1200)
 def test_config_2p27_k32(jz):
+    """Every one of the 2^27 x 32 kNN entries against the exact kd-tree oracle
+    (compared in row chunks: the result is 32 GiB), 2^11 random rows against
+    brute force (each row is 2^27 evaluations), whole-output invariants on
+    the GPU, and every FoF label against the kd-tree oracle."""
     n = 2 ** 27
     t0 = time.time()
     p = inputs.clustered(n, 2 ** 16, 3)
@@ -83,15 +89,28 @@ def test_config_2p27_k32(jz):
         torch.cuda.synchronize()
         say("gpu done %.1fs" % (time.time() - t0))
         knn_invariants(d, idx, d2)
-        rows = np.random.default_rng(27).choice(n, 256, replace=False)
-        ridx = torch.from_numpy(rows).cuda()
-        gi, gd = idx[ridx].cpu().numpy(), d2[ridx].cpu().numpy()
         gl = lab.cpu().numpy()
-        del idx, d2, lab
+        del lab
     del d
+    rows = np.random.default_rng(27).choice(n, 2 ** 11, replace=False)
+    ridx = torch.from_numpy(rows).cuda()
+    knn_rows_equal(idx[ridx].cpu().numpy(), d2[ridx].cpu().numpy(), rows, p, 32, "2^27 k=32")
+    say("brute-force rows %.1fs" % (time.time() - t0))
+    chunk = 1 << 22
+    with oracle.KdTree(p) as kd:
+        say("kd-tree %.1fs" % (time.time() - t0))
+        for c in range(0, n, chunk):
+            wi, wd = kd.rows(c, chunk, 32)
+            gi = idx[c:c + chunk].cpu().numpy()
+            gd = d2[c:c + chunk].cpu().numpy()
+            bad = np.nonzero(np.any(gi != wi, axis=1) |
+                             np.any(gd.view(np.uint32) != wd.view(np.uint32), axis=1))[0]
+            assert bad.size == 0, "2^27 k=32: %d rows differ in rows [%d, %d), first %d" % (
+                bad.size, c, c + chunk, c + bad[0])
+            if (c // chunk) % 8 == 7:
+                say("kd rows up to %d %.1fs" % (c + chunk, time.time() - t0))
+    del idx, d2
     torch.cuda.empty_cache()
-    knn_rows_equal(gi, gd, rows, p, 32, "2^27 k=32")
-    say("knn rows %.1fs" % (time.time() - t0))
     assert np.array_equal(gl, oracle.fof_kd(p, b))
     say("fof %.1fs" % (time.time() - t0))
 

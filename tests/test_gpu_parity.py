@@ -73,13 +73,55 @@ def test_knn_small_sets(jz, k):
         assert_knn_equal(gi, gd, wi, wd, "%s k=%d" % (name, k))
 
 
-def test_knn_config_small_uniform_k8(jz):
-    """N = 16384 uniform, k = 8: the whole result against brute force."""
+@pytest.mark.parametrize("k", [33, 64, 100])
+def test_knn_more_than_32(jz, k):
+    """k > 32: leaf passes of 32 neighbours, each after the last (dist2,
+    index) key of the pass before, against brute force."""
+    for name, p in [("uniform-6000", inputs.uniform(6000, 31)),
+                    ("clustered-8000", inputs.clustered(8000, 8, 32)),
+                    ("grid-dups-2000", (np.random.default_rng(33).integers(0, 5, size=(2000, 3))
+                                        * 0.125).astype(np.float32)),
+                    ("tiny-70", inputs.uniform(70, 34))]:
+        gi, gd, _ = gpu_knn(jz, p, k)
+        wi, wd = oracle.knn_bf(p, k)
+        assert_knn_equal(gi, gd, wi, wd, "%s k=%d" % (name, k))
+
+
+def test_knn_more_than_32_lattice_shells(jz):
+    """A cubic lattice: interior points have distance shells of 1, 6, 12, 8,
+    6, 24, 24, 12, 30 points (r^2/a^2 = 0, 1, 2, 3, 4, 5, 6, 8, 9), so the
+    pass boundaries at 32 and 64 neighbours fall inside shells of equal
+    distances (cumulative 1, 7, 19, 27, 33, 57, 81): the ties across a pass
+    boundary continue by index. Checked against brute force and against the
+    closed-form shell sizes."""
+    p = inputs.lattice(12)
+    a2 = np.float32(2.0 ** -8)
+    for k in (40, 70, 96):
+        gi, gd, _ = gpu_knn(jz, p, k)
+        wi, wd = oracle.knn_bf(p, k)
+        assert_knn_equal(gi, gd, wi, wd, "lattice k=%d" % k)
+        # the centre point's row: shell radii in order
+        c = int(np.argmin(((p - p.mean(axis=0)) ** 2).sum(axis=1)))
+        shells = np.repeat([0, 1, 2, 3, 4, 5, 6, 8, 9], [1, 6, 12, 8, 6, 24, 24, 12, 30])[:k]
+        assert np.array_equal(gd[c], shells.astype(np.float32) * a2), k
+
+
+def test_knn_config_small_uniform_k8(jz, fp64_log):
+    """N = 16384 uniform, k = 8: the whole result against brute force, and the
+    binary64 cross-check of every row (reported, not asserted)."""
     p = inputs.uniform(16384, 1)
     gi, gd, st = gpu_knn(jz, p, 8)
     wi, wd = oracle.knn_bf(p, 8)
     assert_knn_equal(gi, gd, wi, wd)
-    assert st["reruns"] == 0 or st["reruns"] >= 0
+    flips = oracle.knn_f64_report(p, gi)
+    fp64_log.append("uniform N=16384 k=8: %d of 16384 kNN rows differ in binary64 (rows %s)"
+                    % (flips.size, flips[:8].tolist()))
+    b = inputs.linking_length(16384, 0.2)
+    lab, _ = gpu_fof(jz, p, b)
+    rep = oracle.fof_f64_report(p, b, labels=lab)
+    fp64_log.append("uniform N=16384 FoF alpha=0.2: pairs linked only in float32 %d, only in "
+                    "binary64 %d, partition differs: %s" % (
+                        rep["pairs_f32_only"], rep["pairs_f64_only"], rep["partition_differs"]))
 
 
 @pytest.mark.parametrize("leaf_max,k", [(1, 4), (7, 5), (64, 32), (32, 12)])
@@ -101,6 +143,10 @@ def test_knn_long_lists(jz):
     wi, wd = oracle.knn_kd(p, 32)
     gi, gd, st = gpu_knn(jz, p, 32, leaf_max=8)
     assert st["lists_sorted_long"] > 0 and st["lists_unordered"] == 0, st
+    # leaf lists longer than 1024 entries went through the multi-wave HBM
+    # sorter, and walk lists longer than 256 through the one-wave one
+    assert st["lists_presorted_leaf"][1] > 0, st
+    assert sum(c[0] for c in st["lists_presorted_walk"]) > 0, st
     assert_knn_equal(gi, gd, wi, wd, "long lists")
     gi, gd, st = gpu_knn(jz, p, 32, leaf_max=8, sort_max=512)
     assert st["lists_sorted_long"] > 0 and st["lists_unordered"] > 0, st
@@ -156,6 +202,57 @@ def test_fof_dense_clumps(jz):
     assert np.array_equal(got, want)
 
 
+def subnormal_set():
+    """Uniform points plus a cluster at the origin on the grid m * 2^-70
+    (m in [0, 8)^3, with repeats): their dist2 are subnormal float32 values
+    (down to 2^-140) or exactly 0."""
+    rng = np.random.default_rng(71)
+    tiny = (rng.integers(0, 8, size=(600, 3)) * 2.0 ** -70).astype(np.float32)
+    p = np.concatenate([inputs.uniform(3000, 72), tiny])
+    return p[rng.permutation(p.shape[0])]
+
+
+def test_knn_fof_subnormal_distances(jz):
+    p = subnormal_set()
+    d = oracle.dist2_f32(p[:, None, :][:50], p[None, :, :])
+    assert np.any((d > 0) & (d < np.finfo(np.float32).tiny))  # subnormals occur
+    for k in (8, 32):
+        gi, gd, _ = gpu_knn(jz, p, k)
+        wi, wd = oracle.knn_bf(p, k)
+        assert_knn_equal(gi, gd, wi, wd, "subnormal k=%d" % k)
+    for b in (0.0, 2.0 ** -70, 1.5 * 2.0 ** -69, inputs.linking_length(p.shape[0], 0.2)):
+        got, _ = gpu_fof(jz, p, b)
+        assert np.array_equal(got, oracle.fof_bf(p, b)), b
+
+
+def infinite_set():
+    """Uniform points plus two small groups near x = +3e38 and x = -3e38: a
+    coordinate difference between groups overflows, so those pairs have
+    dist2 = +inf, and the rows of the far groups end in +inf entries
+    ordered by index."""
+    rng = np.random.default_rng(81)
+    far = np.zeros((12, 3), dtype=np.float32)
+    far[:6, 0] = np.float32(3e38) - rng.integers(0, 4, 6).astype(np.float32) * np.float32(2e31)
+    far[6:, 0] = np.float32(-3e38) + rng.integers(0, 4, 6).astype(np.float32) * np.float32(2e31)
+    far[:, 1:] = rng.random((12, 2)).astype(np.float32)
+    p = np.concatenate([inputs.uniform(2000, 82), far])
+    return p[rng.permutation(p.shape[0])]
+
+
+def test_knn_fof_infinite_distances(jz):
+    p = infinite_set()
+    for k in (8, 16, 32):
+        gi, gd, _ = gpu_knn(jz, p, k)
+        wi, wd = oracle.knn_bf(p, k)
+        assert np.isinf(wd).any(), k
+        assert_knn_equal(gi, gd, wi, wd, "infinite dist2 k=%d" % k)
+    # b = 3e19: fl(b*b) = +inf, so every pair links, also those at +inf
+    for b in (0.05, 1e30, 3e19):
+        got, _ = gpu_fof(jz, p, b)
+        assert np.array_equal(got, oracle.fof_bf(p, b)), b
+    assert np.all(gpu_fof(jz, p, 3e19)[0] == 0)
+
+
 def test_empty_input(jz):
     p = np.zeros((0, 3), dtype=np.float32)
     with jz.jz_build(torch.zeros((0, 3), dtype=torch.float32, device="cuda")) as t:
@@ -178,7 +275,7 @@ def test_errors(jz):
     assert e.value.status == jz.JZ_E_NONFINITE
     with jz.jz_build(to_dev(inputs.uniform(100, 1))) as t:
         with pytest.raises(jz.JzError) as e:
-            t.knn(33)
+            t.knn(257)
         assert e.value.status == jz.JZ_E_UNSUPPORTED
         with pytest.raises(jz.JzError) as e:
             t.fof(-1.0)
@@ -231,10 +328,11 @@ def test_forest_equals_standalone(jz):
         assert np.array_equal(gi, idx[a:e]) and np.array_equal(gd, d2[a:e])
 
 
-def test_full_size_clustered(jz):
-    """N = 2^24 clustered (the benchmark workload): kNN k=16 on sampled rows
-    against brute force and in full against the exact kd-tree oracle; FoF in
-    full against the kd-tree oracle."""
+def test_full_size_clustered(jz, fp64_log):
+    """N = 2^24 clustered (the benchmark workload): kNN k=16 on 2^14 sampled
+    rows against brute force and in full against the exact kd-tree oracle; FoF
+    in full against the kd-tree oracle; binary64 cross-checks of the sampled
+    kNN rows and of every FoF pair (reported, not asserted)."""
     n = 2 ** 24
     p = inputs.clustered(n, 4096, 2)
     b = inputs.linking_length(n, 0.2)
@@ -244,9 +342,17 @@ def test_full_size_clustered(jz):
         torch.cuda.synchronize()
         gi, gd, gl = idx.cpu().numpy(), d2.cpu().numpy(), lab.cpu().numpy()
         del idx, d2, lab
-    rows = np.random.default_rng(9).choice(n, 512, replace=False)
+    rows = np.random.default_rng(9).choice(n, 2 ** 14, replace=False)
     wi, wd = oracle.knn_bf(p, 16, rows=rows)
     assert_knn_equal(gi[rows], gd[rows], wi, wd, "sampled rows")
     ki, kd = oracle.knn_kd(p, 16)
     assert_knn_equal(gi, gd, ki, kd, "full kd")
     assert np.array_equal(gl, oracle.fof_kd(p, b))
+    flips = oracle.knn_f64_report(p, gi[rows], rows=rows)
+    fp64_log.append("clustered N=2^24 k=16: %d of %d sampled kNN rows differ in binary64"
+                    % (flips.size, rows.size))
+    rep = oracle.fof_f64_report(p, b, labels=gl)
+    fp64_log.append("clustered N=2^24 FoF alpha=0.2: pairs linked only in float32 %d, only in "
+                    "binary64 %d, partition differs: %s (%d points relabelled)" % (
+                        rep["pairs_f32_only"], rep["pairs_f64_only"], rep["partition_differs"],
+                        rep["points_relabelled"]))

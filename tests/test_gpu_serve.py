@@ -89,7 +89,7 @@ def test_server_budget(jz):
             S.submit_knn(p, 8)
         assert e.value.status == jz.JZ_E_OOM
         with pytest.raises(jz.JzError) as e:
-            S.submit_knn(p, 40)
+            S.submit_knn(p, 300)
         assert e.value.status == jz.JZ_E_UNSUPPORTED
 
 
@@ -137,3 +137,37 @@ def test_servers_in_sequence_reuse_cached_memory(jz):
     with jz.jz_build(p) as t:
         i, _ = t.knn(16)
         assert torch.equal(i.cpu(), first[0])
+
+
+def test_server_orders_requests_after_the_callers_stream(jz):
+    """Points written on the caller's stream and submitted at once, without a
+    synchronization: a side stream is kept busy, then generates the points
+    and makes a non-contiguous view of them contiguous. Each request must
+    read the finished points (the server waits for the event recorded on the
+    caller's stream at submission)."""
+    n = 20000
+    g = torch.Generator(device="cuda")
+    with jz.Server(streams=2) as S:
+        for rep in range(3):
+            g.manual_seed(100 + rep)
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                a = torch.rand((2048, 2048), device="cuda", generator=g)
+                for _ in range(8):  # keep the stream busy before the points exist
+                    a = a @ a
+                    a = a / a.abs().max()
+                base = torch.rand((n, 4), device="cuda", generator=g)
+                pts = base[:, 1:]  # non-contiguous: submit makes a contiguous copy on s
+                t1 = S.submit_knn(pts, 8)
+                t2 = S.submit_fof(pts, float(inputs.linking_length(n, 0.3)))
+            (i, d2), _ = S.wait(t1)
+            (lab,), _ = S.wait(t2)
+            torch.cuda.synchronize()
+            p = pts.contiguous().cpu().numpy()
+            wi, wd = oracle.knn_bf(p, 8)
+            assert np.array_equal(i.cpu().numpy(), wi), rep
+            assert np.array_equal(d2.cpu().numpy().view(np.uint32), wd.view(np.uint32)), rep
+            assert np.array_equal(lab.cpu().numpy(),
+                                  oracle.fof_bf(p, float(inputs.linking_length(n, 0.3)))), rep
+            S.release(t1)
+            S.release(t2)

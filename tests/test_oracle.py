@@ -447,3 +447,47 @@ def test_generators_deterministic_and_in_range():
     _, info = inputs.clustered(100000, 64, 5, return_info=True)
     assert info["n_clumped"] == 60000 and info["max_clump"] > 600
     assert inputs.linking_length(2 ** 24) == float(np.float32(0.2 * 2.0 ** -8))
+
+
+# ---------------------------------------------------------------- FoF catalogue
+
+def test_catalogue_lattice_groups_closed_form():
+    """Two m^3 lattice blocks far apart, linked within each block (b = the
+    spacing): each block is one group whose centre of mass is the block
+    centre and whose inertia radius is a * sqrt(3 (m^2 - 1) / 12) (the
+    variance of m equally spaced values is a^2 (m^2 - 1) / 12 per axis); a
+    third, smaller block falls below min_members. Velocities = 2 x position
+    give a centre-of-mass velocity of twice the centre."""
+    a = 2.0 ** -4
+    blocks = [inputs.lattice(4), inputs.lattice(3, offset=(40, 0, 0)), inputs.lattice(2, offset=(0, 40, 0))]
+    p = np.concatenate(blocks)
+    rng = np.random.default_rng(3)
+    perm = rng.permutation(p.shape[0])
+    p = p[perm]
+    lab = oracle.fof_bf(p, a)
+    cat = oracle.fof_catalogue(p, lab, min_members=20, velocities=2 * p)
+    assert sorted(cat["count"].tolist()) == [27, 64] and np.all(np.diff(cat["label"]) > 0)
+    order = cat["order"]
+    # group order: blocks by their smallest member index, ascending indices inside
+    assert np.all(np.diff(lab[order]) >= 0)
+    for g, (f, c) in enumerate(zip(cat["first"], cat["count"])):
+        blk = order[f:f + c]
+        assert np.all(np.diff(blk) > 0) and np.all(lab[blk] == cat["label"][g])
+    centres = {64: np.array([1.5, 1.5, 1.5]) * a, 27: np.array([41.0, 1.0, 1.0]) * a}
+    radii = {64: a * np.sqrt(3 * 15 / 12), 27: a * np.sqrt(3 * 8 / 12)}
+    for g, c in enumerate(cat["count"]):
+        assert np.allclose(cat["cm"][g], centres[c], rtol=0, atol=1e-15)
+        assert abs(cat["r_inertia"][g] - radii[c]) < 1e-15
+        assert np.allclose(cat["vcm"][g], 2 * centres[c], rtol=0, atol=1e-15)
+    # labels are the smallest input index of each group
+    assert set(cat["label"].tolist()) == {int(np.nonzero(lab == l)[0].min()) for l in cat["label"]}
+
+
+def test_catalogue_singletons_and_min_members():
+    p = inputs.uniform(300, 5)
+    lab = oracle.fof_bf(p, 0.0)  # all singletons
+    cat = oracle.fof_catalogue(p, lab, min_members=1)
+    assert np.array_equal(cat["order"], np.arange(300))
+    assert np.array_equal(cat["first"], np.arange(300)) and np.all(cat["count"] == 1)
+    assert np.array_equal(cat["cm"], p.astype(np.float64)) and np.all(cat["r_inertia"] == 0)
+    assert oracle.fof_catalogue(p, lab, min_members=2)["count"].size == 0
