@@ -121,6 +121,23 @@ JZ_API jz_status jz_fof(jz_tree *t, float b, int32_t *label, void *stream);
 /* Release the tree and its device memory (NULL is ignored). */
 JZ_API void jz_tree_free(jz_tree *t);
 
+/* Size of the fixed device array behind jz_knn_noalloc. */
+#define JZ_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+
+/* jz_knn without any device allocation during the call, for callers that
+ * cannot allocate there (tight serving loops, harnesses that forbid
+ * hipMalloc): same arguments, results and errors as jz_knn on a tree built
+ * beforehand with jz_build / jz_forest_build. The call's scratch (walk
+ * counters, per-level lists, work items) is carved from one file-scope device
+ * array of JZ_NOALLOC_SCRATCH_BYTES (128 MiB) that each GPU the library runs
+ * on holds until the process ends; the walk's lists take about 40 bytes per
+ * point at k = 16 on clustered data, so about 3e6 points fit there. A call
+ * needing more returns JZ_E_CAPACITY (use jz_knn). Calls on one GPU share
+ * the array and are serialized by the library (each returns after its work
+ * has finished, like jz_knn); the array keeps the last call's contents and
+ * every call clears what it needs. */
+JZ_API jz_status jz_knn_noalloc(jz_tree *t, int k, int32_t *idx, float *dist2, void *stream);
+
 /* Bytes of device memory the tree holds between calls (sorted points, node
  * planes, splits, top-level lists; 0 for NULL). Scratch memory of a
  * jz_knn / jz_fof call is taken from the allocator during the call and

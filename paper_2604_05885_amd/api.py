@@ -124,6 +124,7 @@ _SIGS = {
     "jz_fof": (ctypes.c_int, [_vp, ctypes.c_float, _vp, _vp]),
     "jz_tree_free": (None, [_vp]),
     "jz_tree_size": (ctypes.c_int64, [_vp]),
+    "jz_knn_noalloc": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp]),
     "jz_forest_build": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int, _vp,
                                        ctypes.POINTER(BuildOpts), ctypes.POINTER(Allocator),
                                        ctypes.POINTER(_vp)]),

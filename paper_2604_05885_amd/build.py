@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libjz.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "build.hip", "knn.hip", "fof.hip", "serve.hip", "tune.hip", "catalogue.hip"]
+SOURCES = ["api.hip", "build.hip", "knn.hip", "fof.hip", "serve.hip", "tune.hip", "noalloc.hip", "catalogue.hip"]
 
 # -ffp-contract=off: no FMA contraction, so distances use the fixed float32
 # expression. Packed FP32 instructions are disabled. Subnormals are kept
