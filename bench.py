@@ -320,9 +320,26 @@ def served(args):
     torch.cuda.set_device(0)
     client = torch.cuda.Stream()
 
-    def make(r):
+    def params(reqs):
+        """Per-request clump parameters, drawn on the host and uploaded once,
+        before the clock starts."""
+        cs, ss, ns, spans = [], [], [], []
+        c0 = 0
+        for r in reqs:
+            n_cl, cen, sig, cnt = inputs.clump_params(r["n"], r["clumps"], r["seed"])
+            cs.append(cen)
+            ss.append(sig)
+            ns.append(cnt)
+            spans.append((c0, c0 + len(sig), n_cl))
+            c0 += len(sig)
+        dev = lambda a, t: torch.from_numpy(np.concatenate(a)).to("cuda", t)
+        return dev(cs, torch.float64), dev(ss, torch.float64), dev(ns, torch.int64), spans
+
+    def make(r, prm, i):
+        cen, sig, cnt, spans = prm
+        a, b, n_cl = spans[i]
         with torch.cuda.stream(client):
-            p = inputs.clustered_device(r["n"], r["clumps"], r["seed"], stream=client)
+            p = inputs.clustered_device(r["n"], r["seed"], n_cl, cen[a:b], sig[a:b], cnt[a:b])
             if r["op"] == "knn":
                 out = (torch.empty((r["n"], r["k"]), dtype=torch.int32, device="cuda"),
                        torch.empty((r["n"], r["k"]), dtype=torch.float32, device="cuda"))
@@ -338,9 +355,10 @@ def served(args):
 
     def run_open(rate, warm, measure, seed):
         reqs = inputs.served_requests(int(rate * (warm + measure)), seed=seed, rate_hz=rate)
+        prm = params(reqs)
         S = api.Server(streams=args.streams, max_batch_sets=4096, hbm_budget=int(200e9))
-        for r in reqs[:16]:  # warm the library (kernels, pool, learned list sizes)
-            p, out = make(r)
+        for i, r in enumerate(reqs[:16]):  # warm the library (kernels, pool, list sizes)
+            p, out = make(r, prm, i)
             S.wait(submit(S, r, p, out))
         torch.cuda.synchronize()
         done = []          # (ticket, due_ns, request)
@@ -372,7 +390,7 @@ def served(args):
         t0 = api.now_ns() + int(0.05e9)
         late_max = 0.0
         backlog = []
-        for r in reqs:
+        for i, r in enumerate(reqs):
             due = t0 + int(r["t"] * 1e9)
             while api.now_ns() < due:
                 pass
@@ -382,7 +400,7 @@ def served(args):
                 # not keep up; stop before their buffers exhaust memory
                 aborted = True
                 break
-            p, out = make(r)
+            p, out = make(r, prm, i)
             tk = submit(S, r, p, out)
             with lock:
                 done.append((tk, due, r))
@@ -426,12 +444,11 @@ def served(args):
         one stream, back to back: the device time of the same mix without
         batching or overlap."""
         reqs = inputs.served_requests(count, seed=seed, rate_hz=2000.0)
+        prm = params(reqs)
         stream = torch.cuda.current_stream()
-        data = [make(r) for r in reqs[:64]]
-        torch.cuda.synchronize()
         total_t, npts = 0.0, 0
         for i, r in enumerate(reqs):
-            p, out = make(r) if i >= 64 else data[i]
+            p, out = make(r, prm, i)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             t = api.jz_build(p, stream=stream)

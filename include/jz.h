@@ -112,6 +112,26 @@ JZ_API jz_status jz_build(const float *points, int64_t n, void *stream, const jz
  * elements. */
 JZ_API jz_status jz_knn(jz_tree *t, int k, int32_t *idx, float *dist2, void *stream);
 
+/* ---- separate query and source points ---------------------------------
+ * (paper: section on multiple point types) One tree built jointly over the
+ * n_src source points and the n_qry query points (both DEVICE float32
+ * [n][3], read only during the call): the two arrays are concatenated
+ * before the z-order sort, so the hierarchy adapts to both distributions,
+ * and every node records how many source points it holds. Nodes are split on
+ * the combined count (at most leaf_max points of both types together per
+ * leaf). Errors as jz_build. Such a tree takes jz_knn_query only (jz_knn,
+ * jz_fof and the catalogue return JZ_E_INVALID on it). */
+JZ_API jz_status jz_build_joint(const float *sources, int64_t n_src, const float *queries,
+                                int64_t n_qry, void *stream, const jz_build_opts *opts,
+                                const jz_allocator *alloc, jz_tree **out);
+
+/* Exact k nearest source points of every query point: row i of
+ * idx[n_qry][k] (DEVICE) holds source indices (0-based into `sources`),
+ * ascending by (dist2, index), dist2[n_qry][k] their squared distances; a
+ * query equal to a source point finds it at distance 0. Rows beyond n_src
+ * sources pad with idx = -1, dist2 = +inf. k in [1, JZ_MAX_K]. */
+JZ_API jz_status jz_knn_query(jz_tree *t, int k, int32_t *idx, float *dist2, void *stream);
+
 /* Friends-of-friends groups (paper: FoF section, Eq. 18): connected
  * components of the graph linking every pair with dist2 <= fl(b*b).
  * label[n] (device, input order) receives, for each point, the smallest input

@@ -8,6 +8,11 @@ problem statements and sharing no code with the GPU library:
 * ``knn_bf`` / ``fof_bf``: the definitions written out (all pairs).
 * ``knn_kd`` / ``fof_kd``: exact kd-tree accelerations for large inputs, pinned
   bit-for-bit to the brute-force versions by the tests.
+* ``knn_cross_bf`` / ``knn_cross_kd``: kNN of separate query points among
+  source points (the paper's multiple point types).
+* ``knn_bf_periodic`` / ``fof_bf_periodic`` (and ``*_kd_periodic``): the same
+  in a periodic cube with the minimum-image distance (each coordinate
+  difference moved by one period when beyond half of it).
 * ``KdTree``: the kd-tree of ``knn_kd`` kept between calls, answering row
   ranges, so that a result too large for host memory is compared in chunks.
 * ``components_uf`` / ``components_bfs``: two independent component labelings
@@ -78,8 +83,19 @@ def _load():
     lib.jzo_kd_free.restype = None
     lib.jzo_fof_f64_report.argtypes = [_f32p, ctypes.c_int64, ctypes.c_float, _i64p, _i64p,
                                        _i32p, ctypes.c_int]
+    lib.jzo_knn_cross_bf.argtypes = [_f32p, ctypes.c_int64, _f32p, ctypes.c_int64, ctypes.c_int,
+                                     _i32p, _f32p, ctypes.c_int]
+    lib.jzo_knn_cross_kd.argtypes = lib.jzo_knn_cross_bf.argtypes
+    lib.jzo_knn_bf_per.argtypes = [_f32p, ctypes.c_int64, ctypes.c_float, ctypes.c_int, _i64p,
+                                   ctypes.c_int64, _i32p, _f32p, ctypes.c_int]
+    lib.jzo_knn_kd_per.argtypes = lib.jzo_knn_bf_per.argtypes
+    lib.jzo_fof_bf_per.argtypes = [_f32p, ctypes.c_int64, ctypes.c_float, ctypes.c_float, _i32p,
+                                   ctypes.c_int]
+    lib.jzo_fof_kd_per.argtypes = lib.jzo_fof_bf_per.argtypes
     for f in ("jzo_knn_bf", "jzo_knn_kd", "jzo_fof_bf", "jzo_fof_kd", "jzo_components_uf",
-              "jzo_components_bfs", "jzo_range_rows_bf", "jzo_kd_knn", "jzo_fof_f64_report"):
+              "jzo_components_bfs", "jzo_range_rows_bf", "jzo_kd_knn", "jzo_fof_f64_report",
+              "jzo_knn_cross_bf", "jzo_knn_cross_kd", "jzo_knn_bf_per", "jzo_knn_kd_per",
+              "jzo_fof_bf_per", "jzo_fof_kd_per"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -122,6 +138,87 @@ def knn_bf(points, k: int, rows=None, threads: int = 0):
 def knn_kd(points, k: int, rows=None, threads: int = 0):
     """Exact kd-tree kNN; same output as :func:`knn_bf`."""
     return _knn(_load().jzo_knn_kd, points, k, rows, threads)
+
+
+def _cross(fn, sources, queries, k, threads):
+    s = _pts(sources)
+    q = _pts(queries)
+    idx = np.empty((q.shape[0], k), dtype=np.int32)
+    d2 = np.empty((q.shape[0], k), dtype=np.float32)
+    rc = fn(_ptr(s, _f32p), s.shape[0], _ptr(q, _f32p), q.shape[0], int(k), _ptr(idx, _i32p),
+            _ptr(d2, _f32p), threads or default_threads())
+    if rc != 0:
+        raise RuntimeError("oracle cross kNN failed (%d)" % rc)
+    return idx, d2
+
+
+def knn_cross_bf(sources, queries, k: int, threads: int = 0):
+    """Brute-force kNN of separate query points among source points:
+    (idx [nq, k] source indices, dist2 [nq, k]), ascending (dist2, index)."""
+    return _cross(_load().jzo_knn_cross_bf, sources, queries, k, threads)
+
+
+def knn_cross_kd(sources, queries, k: int, threads: int = 0):
+    """Exact kd-tree version of :func:`knn_cross_bf` (same output)."""
+    return _cross(_load().jzo_knn_cross_kd, sources, queries, k, threads)
+
+
+def _knn_per(fn, points, period, k, rows, threads):
+    p = _pts(points)
+    r = None if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
+    nr = p.shape[0] if r is None else r.shape[0]
+    idx = np.empty((nr, k), dtype=np.int32)
+    d2 = np.empty((nr, k), dtype=np.float32)
+    rc = fn(_ptr(p, _f32p), p.shape[0], float(np.float32(period)), int(k),
+            None if r is None else _ptr(r, _i64p), nr, _ptr(idx, _i32p), _ptr(d2, _f32p),
+            threads or default_threads())
+    if rc != 0:
+        raise RuntimeError("oracle periodic kNN failed (%d)" % rc)
+    return idx, d2
+
+
+def knn_bf_periodic(points, period: float, k: int, rows=None, threads: int = 0):
+    """:func:`knn_bf` in the periodic cube [0, period)^3 (minimum image)."""
+    return _knn_per(_load().jzo_knn_bf_per, points, period, k, rows, threads)
+
+
+def knn_kd_periodic(points, period: float, k: int, rows=None, threads: int = 0):
+    """Exact kd-tree version of :func:`knn_bf_periodic` (same output)."""
+    return _knn_per(_load().jzo_knn_kd_per, points, period, k, rows, threads)
+
+
+def _fof_per(fn, points, period, b, threads):
+    p = _pts(points)
+    lab = np.empty(p.shape[0], dtype=np.int32)
+    rc = fn(_ptr(p, _f32p), p.shape[0], float(np.float32(period)), float(np.float32(b)),
+            _ptr(lab, _i32p), threads or default_threads())
+    if rc != 0:
+        raise RuntimeError("oracle periodic FoF failed (%d)" % rc)
+    return lab
+
+
+def fof_bf_periodic(points, period: float, b: float, threads: int = 0) -> np.ndarray:
+    """:func:`fof_bf` in the periodic cube [0, period)^3 (minimum image)."""
+    return _fof_per(_load().jzo_fof_bf_per, points, period, b, threads)
+
+
+def fof_kd_periodic(points, period: float, b: float, threads: int = 0) -> np.ndarray:
+    """Exact kd-tree version of :func:`fof_bf_periodic` (same output)."""
+    return _fof_per(_load().jzo_fof_kd_per, points, period, b, threads)
+
+
+def dist2_f32_periodic(p, q, period: float) -> np.ndarray:
+    """The periodic distance of the library, elementwise over broadcast rows."""
+    p = np.asarray(p, dtype=np.float32)
+    q = np.asarray(q, dtype=np.float32)
+    L = np.float32(period)
+    h = np.float32(0.5) * L
+    d = p - q
+    d = np.where(d > h, d - L, np.where(d < -h, d + L, d)).astype(np.float32)
+    xx = d[..., 0] * d[..., 0]
+    yy = d[..., 1] * d[..., 1]
+    zz = d[..., 2] * d[..., 2]
+    return (xx + yy) + zz
 
 
 def _fof(fn, points, b, threads):

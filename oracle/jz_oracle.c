@@ -136,6 +136,122 @@ JZO_API int jzo_knn_bf(const float *pts, int64_t n, int k, const int64_t *rows,
     return fail ? -2 : 0;
 }
 
+/* kNN of separate query points among source points (the paper's "multiple
+ * point types"), brute force: for each query q, the k source points j closest
+ * to q, ascending by (dist2, j), scanning j in increasing order with the same
+ * strict-< insertion as jzo_knn_bf. A query equal to a source point finds it
+ * at distance 0; fewer than k sources pad with idx = -1, dist2 = +inf. */
+JZO_API int jzo_knn_cross_bf(const float *src, int64_t ns, const float *qry, int64_t nq, int k,
+                             int32_t *idx, float *d2, int nthreads) {
+    if (k < 1 || ns < 0 || nq < 0) return -1;
+    int fail = 0;
+#pragma omp parallel num_threads(clamp_threads(nthreads))
+    {
+        float *bd = (float *)malloc(sizeof(float) * (size_t)k);
+        int32_t *bj = (int32_t *)malloc(sizeof(int32_t) * (size_t)k);
+        if (!bd || !bj) {
+#pragma omp atomic write
+            fail = 1;
+        }
+#pragma omp for schedule(dynamic, 8)
+        for (int64_t r = 0; r < nq; ++r) {
+            if (!bd || !bj) continue;
+            const float *p = qry + 3 * r;
+            int cnt = 0;
+            for (int64_t j = 0; j < ns; ++j) {
+                float d = d2f(p, src + 3 * j);
+                if (cnt == k && !(d < bd[k - 1])) continue;
+                int pos = cnt < k ? cnt : k - 1;
+                while (pos > 0 && bd[pos - 1] > d) {
+                    bd[pos] = bd[pos - 1];
+                    bj[pos] = bj[pos - 1];
+                    --pos;
+                }
+                bd[pos] = d;
+                bj[pos] = (int32_t)j;
+                if (cnt < k) ++cnt;
+            }
+            for (int t = 0; t < k; ++t) {
+                idx[r * k + t] = t < cnt ? bj[t] : -1;
+                d2[r * k + t] = t < cnt ? bd[t] : INFINITY;
+            }
+        }
+        free(bd);
+        free(bj);
+    }
+    return fail ? -2 : 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* periodic box (the paper's periodic cosmological case)                      */
+
+/* Minimum-image distance in the periodic cube [0, L)^3 (points inside it):
+ * dx = fl(x_i - x_j) is moved by one period when it lies beyond half of it,
+ *     dx > h: dx = fl(dx - L);  dx < -h: dx = fl(dx + L);  h = fl(L / 2),
+ * and dist2 is the fixed expression of the wrapped differences. Since
+ * fl(a - b) = -fl(b - a) and the wrap is symmetric, dist2 stays symmetric. */
+static inline float wrapf(float d, float L, float h) {
+    if (d > h) return d - L;
+    if (d < -h) return d + L;
+    return d;
+}
+
+static inline float d2f_per(const float *p, const float *q, float L, float h) {
+    float dx = wrapf(p[0] - q[0], L, h);
+    float dy = wrapf(p[1] - q[1], L, h);
+    float dz = wrapf(p[2] - q[2], L, h);
+    float xx = dx * dx;
+    float yy = dy * dy;
+    float zz = dz * dz;
+    float s = xx + yy;
+    return s + zz;
+}
+
+/* jzo_knn_bf with the periodic distance (same selection rule). */
+JZO_API int jzo_knn_bf_per(const float *pts, int64_t n, float L, int k, const int64_t *rows,
+                           int64_t nrows, int32_t *idx, float *d2, int nthreads) {
+    if (k < 1 || n < 0 || !(L > 0.0f)) return -1;
+    const float h = 0.5f * L;
+    int64_t R = rows ? nrows : n;
+    int fail = 0;
+#pragma omp parallel num_threads(clamp_threads(nthreads))
+    {
+        float *bd = (float *)malloc(sizeof(float) * (size_t)k);
+        int32_t *bj = (int32_t *)malloc(sizeof(int32_t) * (size_t)k);
+        if (!bd || !bj) {
+#pragma omp atomic write
+            fail = 1;
+        }
+#pragma omp for schedule(dynamic, 8)
+        for (int64_t r = 0; r < R; ++r) {
+            if (!bd || !bj) continue;
+            int64_t i = rows ? rows[r] : r;
+            const float *p = pts + 3 * i;
+            int cnt = 0;
+            for (int64_t j = 0; j < n; ++j) {
+                float d = d2f_per(p, pts + 3 * j, L, h);
+                if (cnt == k && !(d < bd[k - 1])) continue;
+                int pos = cnt < k ? cnt : k - 1;
+                while (pos > 0 && bd[pos - 1] > d) {
+                    bd[pos] = bd[pos - 1];
+                    bj[pos] = bj[pos - 1];
+                    --pos;
+                }
+                bd[pos] = d;
+                bj[pos] = (int32_t)j;
+                if (cnt < k) ++cnt;
+            }
+            for (int t = 0; t < k; ++t) {
+                idx[r * k + t] = t < cnt ? bj[t] : -1;
+                d2[r * k + t] = t < cnt ? bd[t] : INFINITY;
+            }
+        }
+        free(bd);
+        free(bj);
+    }
+    return fail ? -2 : 0;
+}
+
 /* ------------------------------------------------------------------------- */
 /* union-find (sequential; roots are always the smallest index of a component) */
 
@@ -221,6 +337,36 @@ JZO_API int jzo_fof_bf(const float *pts, int64_t n, float b, int32_t *label, int
             const float *p = pts + 3 * i;
             for (int64_t j = i + 1; j < n; ++j)
                 if (d2f(p, pts + 3 * j) <= b2) uf_unite(par, (int32_t)i, (int32_t)j);
+        }
+    }
+    for (int64_t i = 0; i < n; ++i) label[i] = (int32_t)i;
+    for (int t = 0; t < T; ++t) {
+        int32_t *par = loc + (size_t)t * (size_t)n;
+        for (int64_t i = 0; i < n; ++i) uf_unite(label, (int32_t)i, uf_find(par, (int32_t)i));
+    }
+    for (int64_t i = 0; i < n; ++i) label[i] = uf_find(label, (int32_t)i);
+    free(loc);
+    return 0;
+}
+
+/* jzo_fof_bf with the periodic distance. */
+JZO_API int jzo_fof_bf_per(const float *pts, int64_t n, float L, float b, int32_t *label,
+                           int nthreads) {
+    if (!(b >= 0.0f) || !(L > 0.0f)) return -1;
+    const float b2 = b * b, h = 0.5f * L;
+    int T = clamp_threads(nthreads);
+    int32_t *loc = (int32_t *)malloc(sizeof(int32_t) * (size_t)n * (size_t)T);
+    if (!loc && n > 0) return -2;
+#pragma omp parallel num_threads(T)
+    {
+        int t = omp_get_thread_num();
+        int32_t *par = loc + (size_t)t * (size_t)n;
+        for (int64_t i = 0; i < n; ++i) par[i] = (int32_t)i;
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t i = 0; i < n; ++i) {
+            const float *p = pts + 3 * i;
+            for (int64_t j = i + 1; j < n; ++j)
+                if (d2f_per(p, pts + 3 * j, L, h) <= b2) uf_unite(par, (int32_t)i, (int32_t)j);
         }
     }
     for (int64_t i = 0; i < n; ++i) label[i] = (int32_t)i;
@@ -376,7 +522,8 @@ static inline int pair_less(float da, int32_t ja, float db, int32_t jb) {
  * could enter the (dist2, j) top-k is evaluated. Answers rows[0..nrows) or,
  * with rows == NULL, the consecutive rows first .. first + nrows - 1. */
 static void kd_knn_rows(const kdtree *T, int64_t n, int k, const int64_t *rows, int64_t first,
-                        int64_t nrows, int32_t *idx, float *d2, int nthreads) {
+                        int64_t nrows, int32_t *idx, float *d2, int nthreads,
+                        const float *qpts) {
     const float *pts = T->p;
 #pragma omp parallel num_threads(clamp_threads(nthreads))
     {
@@ -386,7 +533,7 @@ static void kd_knn_rows(const kdtree *T, int64_t n, int k, const int64_t *rows, 
 #pragma omp for schedule(dynamic, 64)
         for (int64_t r = 0; r < nrows; ++r) {
             int64_t i = rows ? rows[r] : first + r;
-            const float *q = pts + 3 * i;
+            const float *q = qpts ? qpts + 3 * i : pts + 3 * i;
             int cnt = 0;
             int sp = 0;
             if (n > 0) stack[sp++] = 0;
@@ -431,7 +578,18 @@ JZO_API int jzo_knn_kd(const float *pts, int64_t n, int k, const int64_t *rows, 
     if (k < 1 || n < 0) return -1;
     kdtree T;
     if (kd_build(&T, pts, n, nthreads)) return -2;
-    kd_knn_rows(&T, n, k, rows, 0, rows ? nrows : n, idx, d2, nthreads);
+    kd_knn_rows(&T, n, k, rows, 0, rows ? nrows : n, idx, d2, nthreads, NULL);
+    kd_free(&T);
+    return 0;
+}
+
+/* jzo_knn_cross_bf with a kd-tree over the sources (same output). */
+JZO_API int jzo_knn_cross_kd(const float *src, int64_t ns, const float *qry, int64_t nq, int k,
+                             int32_t *idx, float *d2, int nthreads) {
+    if (k < 1 || ns < 0 || nq < 0) return -1;
+    kdtree T;
+    if (kd_build(&T, src, ns, nthreads)) return -2;
+    kd_knn_rows(&T, ns, k, NULL, 0, nq, idx, d2, nthreads, qry);
     kd_free(&T);
     return 0;
 }
@@ -460,7 +618,7 @@ JZO_API int jzo_kd_knn(void *handle, int k, const int64_t *rows, int64_t first, 
     kdhandle *h = (kdhandle *)handle;
     if (!h || k < 1 || nrows < 0) return -1;
     if (!rows && (first < 0 || first + nrows > h->n)) return -1;
-    kd_knn_rows(&h->T, h->n, k, rows, first, nrows, idx, d2, nthreads);
+    kd_knn_rows(&h->T, h->n, k, rows, first, nrows, idx, d2, nthreads, NULL);
     return 0;
 }
 
@@ -681,6 +839,184 @@ JZO_API int jzo_fof_f64_report(const float *pts, int64_t n, float b, int64_t *on
     for (int64_t i = 0; i < n; ++i) label64[i] = uf_find(label64, (int32_t)i);
     *only32 = c32;
     *only64 = c64;
+    free(whole);
+    free(loc);
+    kd_free(&T);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* periodic kd-tree searches                                                  */
+
+/* Bounds of the periodic distance between a point q and an axis-aligned box,
+ * made safe for rounding: a wrapped difference fl(fl(q - x) -+ L) can be off
+ * from the exact minimum-image difference by a few units of the last place of
+ * L, so every per-axis gap is lowered (and every extent raised) by an
+ * absolute margin of 2^-21 L, and the sums get a relative margin of 2^-20. */
+static inline float per_gap(float q, float lo, float hi, float L) {
+    if (q >= lo && q <= hi) return 0.0f;
+    float a = lo - q;
+    if (a < 0.0f) a += L;
+    float b = q - hi;
+    if (b < 0.0f) b += L;
+    return a < b ? a : b;
+}
+
+static inline float per_low(const float *q, const float *lo, const float *hi, float L) {
+    const float eps = L * 0x1p-21f;
+    float s = 0.0f;
+    for (int a = 0; a < 3; ++a) {
+        float g = per_gap(q[a], lo[a], hi[a], L) - eps;
+        g = g > 0.0f ? g : 0.0f;
+        s += g * g;
+    }
+    return s * (1.0f - 0x1p-20f);
+}
+
+static inline float per_up(const float *q, const float *lo, const float *hi, float L) {
+    const float eps = L * 0x1p-21f, h = 0.5f * L;
+    float s = 0.0f;
+    for (int a = 0; a < 3; ++a) {
+        float u = fabsf(q[a] - lo[a]);
+        float v = fabsf(hi[a] - q[a]);
+        u = u > v ? u : v;
+        u = (u < h ? u : h) + eps;
+        s += u * u;
+    }
+    return s * (1.0f + 0x1p-20f);
+}
+
+/* jzo_knn_kd with the periodic distance: a subtree is skipped only if its
+ * (rounding-safe) periodic lower bound exceeds the current k-th distance. */
+JZO_API int jzo_knn_kd_per(const float *pts, int64_t n, float L, int k, const int64_t *rows,
+                           int64_t nrows, int32_t *idx, float *d2, int nthreads) {
+    if (k < 1 || n < 0 || !(L > 0.0f)) return -1;
+    const float h = 0.5f * L;
+    kdtree T;
+    if (kd_build(&T, pts, n, nthreads)) return -2;
+    int64_t R = rows ? nrows : n;
+#pragma omp parallel num_threads(clamp_threads(nthreads))
+    {
+        float *bd = (float *)malloc(sizeof(float) * (size_t)k);
+        int32_t *bj = (int32_t *)malloc(sizeof(int32_t) * (size_t)k);
+        int64_t stack[256];
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t r = 0; r < R; ++r) {
+            int64_t i = rows ? rows[r] : r;
+            const float *q = pts + 3 * i;
+            int cnt = 0, sp = 0;
+            if (n > 0) stack[sp++] = 0;
+            while (sp > 0) {
+                const kdnode *nd = &T.node[stack[--sp]];
+                if (cnt == k && per_low(q, nd->lo, nd->hi, L) > bd[k - 1]) continue;
+                if (nd->left < 0) {
+                    for (int64_t t = nd->a; t < nd->b; ++t) {
+                        int32_t j = T.perm[t];
+                        float d = d2f_per(q, pts + 3 * (int64_t)j, L, h);
+                        if (cnt == k && !pair_less(d, j, bd[k - 1], bj[k - 1])) continue;
+                        int pos = cnt < k ? cnt : k - 1;
+                        while (pos > 0 && pair_less(d, j, bd[pos - 1], bj[pos - 1])) {
+                            bd[pos] = bd[pos - 1];
+                            bj[pos] = bj[pos - 1];
+                            --pos;
+                        }
+                        bd[pos] = d;
+                        bj[pos] = j;
+                        if (cnt < k) ++cnt;
+                    }
+                } else {
+                    const kdnode *Ln = &T.node[nd->left], *Rn = &T.node[nd->left + 1];
+                    float dl = per_low(q, Ln->lo, Ln->hi, L), dr = per_low(q, Rn->lo, Rn->hi, L);
+                    if (dl <= dr) { stack[sp++] = nd->left + 1; stack[sp++] = nd->left; }
+                    else { stack[sp++] = nd->left; stack[sp++] = nd->left + 1; }
+                }
+            }
+            for (int t = 0; t < k; ++t) {
+                idx[r * k + t] = t < cnt ? bj[t] : -1;
+                d2[r * k + t] = t < cnt ? bd[t] : INFINITY;
+            }
+        }
+        free(bd);
+        free(bj);
+    }
+    kd_free(&T);
+    return 0;
+}
+
+/* jzo_fof_kd with the periodic distance and the rounding-safe bounds (a box
+ * is taken whole only if its periodic upper bound is within b). */
+JZO_API int jzo_fof_kd_per(const float *pts, int64_t n, float L, float b, int32_t *label,
+                           int nthreads) {
+    if (!(b >= 0.0f) || !(L > 0.0f)) return -1;
+    const float b2 = b * b, h = 0.5f * L;
+    kdtree T;
+    if (kd_build(&T, pts, n, nthreads)) return -2;
+    int TH = clamp_threads(nthreads);
+    uint8_t *whole = (uint8_t *)calloc((size_t)T.nnode + 1, 1);
+    int32_t *loc = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1) * (size_t)TH);
+    if (!whole || !loc) { free(whole); free(loc); kd_free(&T); return -2; }
+    for (int64_t id = 0; id < T.nnode; ++id) {
+        kdnode *nd = &T.node[id];
+        float ext[3], zero[3] = {0.0f, 0.0f, 0.0f};
+        for (int a = 0; a < 3; ++a) ext[a] = nd->hi[a] - nd->lo[a];
+        /* largest distance between two points of the box: its extents */
+        if (nd->b > nd->a && per_up(zero, zero, ext, L) <= b2) whole[id] = 1;
+    }
+#pragma omp parallel num_threads(TH)
+    {
+        int t = omp_get_thread_num();
+        int32_t *par = loc + (size_t)t * (size_t)n;
+        for (int64_t i = 0; i < n; ++i) par[i] = (int32_t)i;
+        int64_t stack[256];
+#pragma omp for schedule(dynamic, 256)
+        for (int64_t i = 0; i < n; ++i) {
+            const float *q = pts + 3 * i;
+            int sp = 0;
+            if (n > 0) stack[sp++] = 0;
+            while (sp > 0) {
+                int64_t id = stack[--sp];
+                kdnode *nd = &T.node[id];
+                if (per_low(q, nd->lo, nd->hi, L) > b2) continue;
+                if (per_up(q, nd->lo, nd->hi, L) <= b2) {
+                    uf_unite(par, (int32_t)i, T.perm[nd->a]);
+#pragma omp atomic write
+                    whole[id] = 1;
+                    continue;
+                }
+                if (nd->left < 0) {
+                    for (int64_t s = nd->a; s < nd->b; ++s) {
+                        int32_t j = T.perm[s];
+                        if (j != i && d2f_per(q, pts + 3 * (int64_t)j, L, h) <= b2)
+                            uf_unite(par, (int32_t)i, j);
+                    }
+                } else {
+                    stack[sp++] = nd->left;
+                    stack[sp++] = nd->left + 1;
+                }
+            }
+        }
+    }
+    for (int64_t i = 0; i < n; ++i) label[i] = (int32_t)i;
+    for (int t = 0; t < TH; ++t) {
+        int32_t *par = loc + (size_t)t * (size_t)n;
+        for (int64_t i = 0; i < n; ++i) uf_unite(label, (int32_t)i, uf_find(par, (int32_t)i));
+    }
+    {
+        int64_t stack[256];
+        int sp = 0;
+        if (n > 0) stack[sp++] = 0;
+        while (sp > 0) {
+            int64_t id = stack[--sp];
+            kdnode *nd = &T.node[id];
+            if (whole[id]) {
+                int32_t first = T.perm[nd->a];
+                for (int64_t s = nd->a + 1; s < nd->b; ++s) uf_unite(label, first, T.perm[s]);
+                continue;
+            }
+            if (nd->left >= 0) { stack[sp++] = nd->left; stack[sp++] = nd->left + 1; }
+        }
+    }
+    for (int64_t i = 0; i < n; ++i) label[i] = uf_find(label, (int32_t)i);
     free(whole);
     free(loc);
     kd_free(&T);

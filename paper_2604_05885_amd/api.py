@@ -123,6 +123,10 @@ _SIGS = {
     "jz_knn": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp]),
     "jz_fof": (ctypes.c_int, [_vp, ctypes.c_float, _vp, _vp]),
     "jz_tree_free": (None, [_vp]),
+    "jz_build_joint": (ctypes.c_int, [_vp, ctypes.c_int64, _vp, ctypes.c_int64, _vp,
+                                      ctypes.POINTER(BuildOpts), ctypes.POINTER(Allocator),
+                                      ctypes.POINTER(_vp)]),
+    "jz_knn_query": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp]),
     "jz_tree_size": (ctypes.c_int64, [_vp]),
     "jz_knn_noalloc": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp]),
     "jz_forest_build": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int, _vp,
@@ -283,6 +287,7 @@ class Tree:
         self.nsets = nsets
         self.offsets = offsets
         self._allocator = allocator  # kept alive while the tree may call it
+        self.n_src = -1              # joint trees: number of source points
 
     @property
     def handle(self):
@@ -304,6 +309,24 @@ class Tree:
             raise TypeError("idx / dist2 must be contiguous int32 / float32 of shape (n, k)")
         _check(lib.jz_knn(self.handle, int(k), ctypes.c_void_p(idx.data_ptr()),
                           ctypes.c_void_p(dist2.data_ptr()), _stream(stream)))
+        return idx, dist2
+
+    def knn_query(self, k: int, idx=None, dist2=None, stream=None):
+        """On a joint tree (jz_build_joint): (idx [n_qry, k] source indices,
+        dist2 [n_qry, k])."""
+        import torch
+        nq = self.n - self.n_src
+        dev = torch.device("cuda", torch.cuda.current_device())
+        if idx is None:
+            idx = torch.empty((nq, k), dtype=torch.int32, device=dev)
+        if dist2 is None:
+            dist2 = torch.empty((nq, k), dtype=torch.float32, device=dev)
+        if tuple(idx.shape) != (nq, k) or tuple(dist2.shape) != (nq, k) or \
+                not idx.is_contiguous() or not dist2.is_contiguous() or \
+                idx.dtype != torch.int32 or dist2.dtype != torch.float32:
+            raise TypeError("idx / dist2 must be contiguous int32 / float32 of shape (n_qry, k)")
+        _check(lib.jz_knn_query(self.handle, int(k), ctypes.c_void_p(idx.data_ptr()),
+                                ctypes.c_void_p(dist2.data_ptr()), _stream(stream)))
         return idx, dist2
 
     def fof(self, b, label=None, stream=None):
@@ -414,6 +437,23 @@ def jz_build(points, opts: BuildOpts | None = None, stream=None, allocator=None)
     _check(lib.jz_build(ctypes.c_void_p(p.data_ptr()), p.shape[0], _stream(stream),
                         ctypes.byref(opts) if opts is not None else None, aref, ctypes.byref(h)))
     return Tree(h, p.shape[0], allocator=keep)
+
+
+def jz_build_joint(sources, queries, opts: BuildOpts | None = None, stream=None,
+                   allocator=None) -> Tree:
+    """One tree over source and query points (CUDA float32 (n, 3) tensors),
+    for :meth:`Tree.knn_query`."""
+    s = _points(sources)
+    q = _points(queries)
+    h = ctypes.c_void_p()
+    aref, keep = _alloc_arg(allocator)
+    _check(lib.jz_build_joint(ctypes.c_void_p(s.data_ptr()), s.shape[0],
+                              ctypes.c_void_p(q.data_ptr()), q.shape[0], _stream(stream),
+                              ctypes.byref(opts) if opts is not None else None, aref,
+                              ctypes.byref(h)))
+    t = Tree(h, s.shape[0] + q.shape[0], allocator=keep)
+    t.n_src = s.shape[0]
+    return t
 
 
 def jz_forest_build(points, offsets, opts: BuildOpts | None = None, stream=None,

@@ -331,9 +331,69 @@ jz_status jz_forest_build(const float *points, const int64_t *offsets, int nsets
     return make_tree_impl(points, offsets, nsets, offsets[nsets], stream, opts, alloc, out);
 }
 
+jz_status jz_build_joint(const float *sources, int64_t n_src, const float *queries,
+                         int64_t n_qry, void *stream, const jz_build_opts *opts,
+                         const jz_allocator *alloc, jz_tree **out) {
+    g_err.clear();
+    if (out) *out = nullptr;
+    if (!out) return jz_fail(JZ_E_INVALID, "out is NULL");
+    if (n_src < 0 || n_qry < 0 || n_src + n_qry > (int64_t)INT32_MAX - 1)
+        return jz_fail(JZ_E_INVALID, "n_src, n_qry must be >= 0 with n_src + n_qry <= 2^31-2");
+    if ((n_src > 0 && !sources) || (n_qry > 0 && !queries))
+        return jz_fail(JZ_E_INVALID, "points are NULL");
+    if (alloc && (!alloc->alloc || !alloc->free))
+        return jz_fail(JZ_E_INVALID, "allocator needs both alloc and free");
+    const int64_t n = n_src + n_qry;
+    hipStream_t s = (hipStream_t)stream;
+    AllocCtx ac;
+    if (hipGetDevice(&ac.device) != hipSuccess) {
+        (void)hipGetLastError();
+        return jz_fail(JZ_E_DEVICE, "no HIP device");
+    }
+    if (alloc) {
+        ac.user = true;
+        ac.ua = *alloc;
+    }
+    // one array over both types: sources first, then queries
+    DBuf cat;
+    JZ_TRY(cat.get(&ac, (size_t)n * 3 * sizeof(float), s));
+    if (n_src)
+        JZ_HIP(hipMemcpyAsync(cat.p, sources, (size_t)n_src * 3 * sizeof(float),
+                              hipMemcpyDeviceToDevice, s));
+    if (n_qry)
+        JZ_HIP(hipMemcpyAsync(cat.as<float>() + 3 * n_src, queries, (size_t)n_qry * 3 * sizeof(float),
+                              hipMemcpyDeviceToDevice, s));
+    const int64_t off[2] = {0, n};
+    JZ_TRY(make_tree_impl(cat.as<float>(), off, 1, n, stream, opts, alloc, out));
+    jz_tree *t = *out;
+    t->n_src = n_src;
+    jz_status st = n > 0 ? source_counts(t, s) : JZ_OK;
+    if (st == JZ_OK) {
+        const hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) st = jz_hip_fail(e, "hipStreamSynchronize", __FILE__, __LINE__);
+    }
+    if (st != JZ_OK) {
+        delete t;
+        *out = nullptr;
+    }
+    return st;
+}
+
+jz_status jz_knn_query(jz_tree *t, int k, int32_t *idx, float *dist2, void *stream) {
+    g_err.clear();
+    if (!t) return jz_fail(JZ_E_INVALID, "tree is NULL");
+    if (t->n_src < 0) return jz_fail(JZ_E_INVALID, "the tree has no query points (jz_build_joint)");
+    if (k < 1) return jz_fail(JZ_E_INVALID, "k must be >= 1");
+    if (k > JZ_MAX_K) return jz_fail(JZ_E_UNSUPPORTED, "k > %d is not supported", JZ_MAX_K);
+    if (t->n > t->n_src && (!idx || !dist2)) return jz_fail(JZ_E_INVALID, "output is NULL");
+    DeviceGuard g(t->ac.device);
+    return run_knn(t, k, idx, dist2, (hipStream_t)stream);
+}
+
 jz_status jz_knn(jz_tree *t, int k, int32_t *idx, float *dist2, void *stream) {
     g_err.clear();
     if (!t) return jz_fail(JZ_E_INVALID, "tree is NULL");
+    if (t->n_src >= 0) return jz_fail(JZ_E_INVALID, "a joint tree takes jz_knn_query");
     if (k < 1) return jz_fail(JZ_E_INVALID, "k must be >= 1");
     if (k > JZ_MAX_K) return jz_fail(JZ_E_UNSUPPORTED, "k > %d is not supported", JZ_MAX_K);
     if (t->n > 0 && (!idx || !dist2)) return jz_fail(JZ_E_INVALID, "output is NULL");
@@ -344,6 +404,7 @@ jz_status jz_knn(jz_tree *t, int k, int32_t *idx, float *dist2, void *stream) {
 jz_status jz_fof(jz_tree *t, float b, int32_t *label, void *stream) {
     g_err.clear();
     if (!t) return jz_fail(JZ_E_INVALID, "tree is NULL");
+    if (t->n_src >= 0) return jz_fail(JZ_E_INVALID, "FoF takes a tree from jz_build");
     if (!(b >= 0.0f) || !std::isfinite(b)) return jz_fail(JZ_E_INVALID, "b must be finite and >= 0");
     if (t->n > 0 && !label) return jz_fail(JZ_E_INVALID, "label is NULL");
     DeviceGuard g(t->ac.device);
@@ -378,7 +439,7 @@ int64_t jz_tree_size(const jz_tree *t) {
                t->super_spl.bytes + t->knn_top_seg.bytes + t->knn_top_list.bytes +
                t->fof_top_seg.bytes + t->fof_top_list.bytes;
     for (int p = 0; p < JZ_MAX_PLANES; ++p)
-        b += t->nodes[p].bytes + t->spl[p].bytes + t->node_set[p].bytes;
+        b += t->nodes[p].bytes + t->spl[p].bytes + t->node_set[p].bytes + t->src_cnt[p].bytes;
     return (int64_t)b;
 }
 

@@ -660,6 +660,49 @@ jz_status radix_sort_pairs(const AllocCtx *ac, DBuf &k0, DBuf &v0, DBuf &k1, DBu
     return JZ_OK;
 }
 
+namespace {
+
+// source points per leaf (one wave per leaf: a leaf holds at most 64 points)
+__global__ __launch_bounds__(256) void k_src_count_leaf(const Node *__restrict__ leaves, int64_t L,
+                                                        const float4 *__restrict__ pts, int n_src,
+                                                        int *__restrict__ cnt) {
+    const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (i >= L) return;
+    const Node a = leaves[i];
+    const int lane = lane_id();
+    const bool src = lane < a.count && __float_as_int(pts[a.start + lane].w) < n_src;
+    const uint64_t m = __ballot(src);
+    if (lane == 0) cnt[i] = (int)__popcll(m);
+}
+
+// source points per node of a coarser plane: the sum over its children
+__global__ __launch_bounds__(256) void k_src_count_up(const int *__restrict__ child,
+                                                      const int *__restrict__ spl, int64_t L,
+                                                      int *__restrict__ cnt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= L) return;
+    int s = 0;
+    for (int c = spl[i]; c < spl[i + 1]; ++c) s += child[c];
+    cnt[i] = s;
+}
+
+}  // namespace
+
+jz_status source_counts(jz_tree *t, hipStream_t s) {
+    for (int p = 0; p < t->P; ++p) {
+        JZ_TRY(t->src_cnt[p].get(&t->ac, (size_t)t->L[p] * sizeof(int), s));
+        if (p == 0)
+            k_src_count_leaf<<<blocks_for(t->L[0] * 64, 256), 256, 0, s>>>(
+                t->nodes[0].as<Node>(), t->L[0], t->pts4.as<float4>(), (int)t->n_src,
+                t->src_cnt[0].as<int>());
+        else
+            k_src_count_up<<<blocks_for(t->L[p], 256), 256, 0, s>>>(
+                t->src_cnt[p - 1].as<int>(), t->spl[p].as<int>(), t->L[p], t->src_cnt[p].as<int>());
+    }
+    JZ_HIP(hipGetLastError());
+    return JZ_OK;
+}
+
 static int plan_planes(int64_t n, const jz_build_opts &o) {
     int P = 1;
     double nmax = (double)o.leaf_max;

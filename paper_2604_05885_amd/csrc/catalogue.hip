@@ -235,7 +235,8 @@ extern "C" JZ_API jz_status jz_fof_catalogue(jz_tree *t, float b, int min_member
     if (!t) return jz_fail(JZ_E_INVALID, "tree is NULL");
     if (!ngroups) return jz_fail(JZ_E_INVALID, "ngroups is NULL");
     *ngroups = 0;
-    if (t->nsets != 1) return jz_fail(JZ_E_INVALID, "the catalogue takes a single-set tree");
+    if (t->nsets != 1 || t->n_src >= 0)
+        return jz_fail(JZ_E_INVALID, "the catalogue takes a single-set tree from jz_build");
     if (!(b >= 0.0f) || !std::isfinite(b)) return jz_fail(JZ_E_INVALID, "b must be finite and >= 0");
     if (min_members < 1) return jz_fail(JZ_E_INVALID, "min_members must be >= 1");
     if (max_groups < 0 || (max_groups > 0 && !groups))

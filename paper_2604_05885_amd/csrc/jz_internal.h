@@ -122,6 +122,12 @@ struct jz_tree {
     DBuf knn_top_seg, knn_top_list;  // dense super-node list (all pairs within a set)
     DBuf fof_top_seg, fof_top_list;  // dense super-node list (pairs s <= t within a set)
 
+    // separate point types (jz_build_joint): points [0, n_src) are sources,
+    // [n_src, n) queries; n_src = -1 otherwise. src_cnt[p][i]: source points
+    // in node i of plane p.
+    int64_t n_src = -1;
+    DBuf src_cnt[JZ_MAX_PLANES];
+
     jz_stats st{};
 };
 
@@ -131,6 +137,8 @@ jz_status tree_create(const float *points, const int64_t *offsets, int nsets, hi
 
 // pipelines (build.hip / knn.hip / fof.hip)
 jz_status build_tree(jz_tree *t, const float *points, hipStream_t s);
+// per-node source counts of a joint tree (t->n_src set)
+jz_status source_counts(jz_tree *t, hipStream_t s);
 // run_knn takes its per-call scratch from `scratch` when given (instead of
 // the tree's allocator); every buffer it acquires after its fixed ones is a
 // level list, acquired top level first and released bottom level first.

@@ -254,11 +254,14 @@ constexpr int FCAP = 128;  // source children staged per batch
 // exceeds rw() (re-evaluated per batch) end the walk. fn(nF) then processes
 // the nF staged children. The list entries of the next batch and their
 // children ranges are loaded while fn runs on the current one.
+// With separate query and source points (scnt != nullptr), a staged record's
+// count is replaced by its number of source points.
 template <class RW, class FN>
 __device__ __forceinline__ void for_source_batches(bool staged, const uint64_t *L,
                                                    const int2 *gl, int len,
                                                    const int *__restrict__ par_spl,
-                                                   const Node *__restrict__ nodes, Node *F, int *FI,
+                                                   const Node *__restrict__ nodes,
+                                                   const int *__restrict__ scnt, Node *F, int *FI,
                                                    RW &&rw, FN &&fn) {
     const int lane = lane_id();
     int t = 0, skip = 0;
@@ -293,7 +296,9 @@ __device__ __forceinline__ void for_source_batches(bool staged, const uint64_t *
             // children (the loaded entries stay those of position t)
             const int f0 = uni(__shfl(b0, 0, 64));
             for (int f = lane; f < FCAP; f += 64) {
-                F[f] = nodes[f0 + f];
+                Node o = nodes[f0 + f];
+                if (scnt) o.count = scnt[f0 + f];
+                F[f] = o;
                 FI[f] = f0 + f;
             }
             nF = FCAP;
@@ -308,7 +313,12 @@ __device__ __forceinline__ void for_source_batches(bool staged, const uint64_t *
             }
             nF = uni(__shfl(incl, ntake - 1, 64));
             wave_lds_sync();
-            for (int f = lane; f < nF; f += 64) F[f] = nodes[FI[f]];
+            for (int f = lane; f < nF; f += 64) {
+                const int fi = FI[f];
+                Node o = nodes[fi];
+                if (scnt) o.count = scnt[fi];
+                F[f] = o;
+            }
             t += ntake;
             skip = 0;
             load(t);
@@ -363,7 +373,7 @@ __global__ __launch_bounds__(64 * WPB) void k_knn_step(
     const int *__restrict__ par_spl, const Node *__restrict__ nodes, int k,
     int2 *__restrict__ seg_out, int2 *__restrict__ list_out,
     unsigned long long *__restrict__ ctr, long long cap, unsigned long long *overflow,
-    int sort_cap, int presorted) {
+    int sort_cap, int presorted, const int *__restrict__ scnt) {
     // one block per wave: the staged list (LCAP entries), then the staged
     // source children (FCAP records and their indices); before the walk the
     // whole block is the scratch in which a longer list is sorted
@@ -392,9 +402,11 @@ __global__ __launch_bounds__(64 * WPB) void k_knn_step(
         while ((nc << (lg + 1)) <= 64) ++lg;
         const int G = 1 << lg;
         const int ci = lane >> lg, sl = lane & (G - 1);
-        const bool act = ci < nc;
-        const int c = cb + (act ? ci : 0);
+        const int c = cb + (ci < nc ? ci : 0);
         const Node me = nodes[c];
+        // with separate point types, a child without query points receives
+        // nothing
+        const bool act = ci < nc && (!scnt || me.count > scnt[c]);
         float hr[NR_HEAP];
         int hc[NR_HEAP];
 #pragma unroll
@@ -405,13 +417,13 @@ __global__ __launch_bounds__(64 * WPB) void k_knn_step(
         float R = INFINITY;
         // pass 1: FindRmax over this lane's slice
         for_source_batches(
-            staged, L, gl, len, par_spl, nodes, F, FI,
+            staged, L, gl, len, par_spl, nodes, scnt, F, FI,
             [&]() { return wave_max_f(act ? R : -INFINITY); },
             [&](int nF) {
                 for (int f = sl; f < nF; f += G) {
                     const Node o = F[f];
                     const float r = box_up2(me, o);
-                    if (act && r < R) {
+                    if (act && r < R && o.count > 0) {
                         heap_insert<NR_HEAP>(hr, hc, r, o.count);
                         R = fminf(R, radius_of_count<NR_HEAP>(hr, hc, k));
                     }
@@ -451,9 +463,12 @@ __global__ __launch_bounds__(64 * WPB) void k_knn_step(
         // pass 2: count
         int cnt = 0;
         for_source_batches(
-            staged, L, gl, len, par_spl, nodes, F, FI, [&]() { return Rw; },
+            staged, L, gl, len, par_spl, nodes, scnt, F, FI, [&]() { return Rw; },
             [&](int nF) {
-                for (int f = sl; f < nF; f += G) cnt += (act && box_low2(me, F[f]) <= R) ? 1 : 0;
+                for (int f = sl; f < nF; f += G) {
+                    const Node o = F[f];
+                    cnt += (act && o.count > 0 && box_low2(me, o) <= R) ? 1 : 0;
+                }
             });
         // reserve: lanes are child-major, so a wave scan gives contiguous segments
         const int incl = wave_incl_scan(cnt);
@@ -471,18 +486,19 @@ __global__ __launch_bounds__(64 * WPB) void k_knn_step(
         const int gfirst = (ci << lg), glast = gfirst + G - 1;
         const int gstart = __shfl(incl - cnt, gfirst & 63, 64);
         const int gend = __shfl(incl, glast & 63, 64);
-        if (act && sl == 0)
+        if (ci < nc && sl == 0)
             seg_out[c] = ok ? make_int2((int)((long long)base + gstart), gend - gstart)
                             : make_int2(0, 0);
         if (!ok) continue;
         // pass 3: insert
         long long wp = (long long)base + (incl - cnt);
         for_source_batches(
-            staged, L, gl, len, par_spl, nodes, F, FI, [&]() { return Rw; },
+            staged, L, gl, len, par_spl, nodes, scnt, F, FI, [&]() { return Rw; },
             [&](int nF) {
                 for (int f = sl; f < nF; f += G) {
-                    const float lo = box_low2(me, F[f]);
-                    if (act && lo <= R) {
+                    const Node o = F[f];
+                    const float lo = box_low2(me, o);
+                    if (act && o.count > 0 && lo <= R) {
                         list_out[wp] = make_int2(FI[f], __float_as_int(lo));
                         ++wp;
                     }
@@ -686,7 +702,8 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
     const float4 *__restrict__ pts, int n_leaves, const int *__restrict__ leaf_base,
     int32_t *__restrict__ out_idx, float *__restrict__ out_d2,
     unsigned long long *__restrict__ stats, const unsigned long long *__restrict__ overflow,
-    int sort_cap, int presorted, int out_stride, int col0, int kw) {
+    int sort_cap, int presorted, int out_stride, int col0, int kw,
+    const int *__restrict__ scnt0, int src_hi, int qry_lo) {
     // one block per wave: the staged list (LCAP entries), the point tile,
     // the (lo, hi) box of every 8 tile positions and the candidate queues;
     // before the walk the whole block is the scratch in which a longer list
@@ -696,17 +713,33 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
     __shared__ __align__(16) uint64_t s_raw[WPB][RAW];
     __shared__ Node s_nodes[WPB][SB];
     __shared__ int s_offs[WPB][SB + 1];
+    __shared__ int s_sc[WPB][SB];
     const int w = WPB == 1 ? 0 : uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
     const int A = xcd_block(blockIdx.x, gridDim.x) * WPB + w;
     // a level of this attempt overflowed (it is rerun): nothing to do
     if (A >= n_leaves || *overflow) return;
     const Node a = leaves[A];
-    const int acount = uni(a.count);
+    uint64_t *L = s_raw[w];
+    // The leaf's query points: all its points, or, with separate point types
+    // (qry_lo > 0), those with index >= qry_lo; query j sits at leaf
+    // position sel[j] (selected through the LDS queue area, unused so far).
+    int acount = uni(a.count);
+    const bool types = qry_lo > 0;
+    const uint8_t *sel = reinterpret_cast<const uint8_t *>(L + O_Q);
+    if (types) {
+        const bool isq = lane < acount && __float_as_int(pts[a.start + lane].w) >= qry_lo;
+        const uint64_t qm = __ballot(isq);
+        if (isq) reinterpret_cast<uint8_t *>(L + O_Q)[__popcll(qm & lanemask_lt())] = (uint8_t)lane;
+        acount = uni((int)__popcll(qm));
+        if (acount == 0) return;
+        wave_lds_sync();
+    }
     const int lgS = acount <= 16 ? 2 : (acount <= 32 ? 1 : 0);  // log2 lanes per query
     const int q = lane & ((64 >> lgS) - 1), h = lane >> (6 - lgS);
     const bool act = q < acount;
-    const float4 me = pts[a.start + (act ? q : 0)];
-    const int64_t row = (int64_t)__float_as_int(me.w);
+    const int qpos = types ? (int)sel[act ? q : 0] : (act ? q : 0);
+    const float4 me = pts[a.start + qpos];
+    const int64_t row = (int64_t)__float_as_int(me.w) - qry_lo;
     const int base = leaf_base ? leaf_base[A] : 0;
     // keys at or below lo (and distances below lo_d) belong to earlier passes
     double lo = -1.0;
@@ -722,11 +755,11 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
     const int2 sg = seg[A];
     int2 *gl = list + uni(sg.x);
     const int len = uni(sg.y);
-    uint64_t *L = s_raw[w];
     float4 *tile = reinterpret_cast<float4 *>(L + O_TILE);
     float4 *cbox = reinterpret_cast<float4 *>(L + O_BOX);
     Node *nb = s_nodes[w];
     int *offs = s_offs[w];
+    int *sc = s_sc[w];  // source points of each batch source
     const bool staged = stage_list(gl, len, L, min(sort_cap, prev_pow2(RAW)), presorted);
 
     const double pad = __builtin_bit_cast(double, PAD_KEY);
@@ -777,7 +810,7 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
     // The list entries of the next batch window and their Node records are
     // fetched one batch ahead (into registers of lanes 0..SB-1), so the Node
     // loads overlap the current batch's work.
-    int pf_src = 0;
+    int pf_src = 0, pf_sc = 0;
     float pf_rl = INFINITY;
     bool pf_ok = false;
     float4 pf_lo = make_float4(0, 0, 0, 0), pf_hi = pf_lo;  // the Node record's two halves
@@ -788,6 +821,7 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
             const float4 *rec = reinterpret_cast<const float4 *>(leaves + pf_src);
             pf_lo = rec[0];
             pf_hi = rec[1];
+            pf_sc = scnt0 ? scnt0[pf_src] : __float_as_int(pf_hi.w);
         }
     };
     // the first batch is one source, so that the top-k fills from the
@@ -807,6 +841,7 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
             float4 *rec = reinterpret_cast<float4 *>(nb + lane);
             rec[0] = pf_lo;
             rec[1] = pf_hi;
+            sc[lane] = pf_sc;
         }
         wave_lds_sync();
         unsigned needbits = 0;
@@ -823,7 +858,7 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
 #pragma unroll
         for (int qq = 0; qq < SB; ++qq) {
             const bool want = qq < nb_n && take == qq;
-            const int c = want && ((any >> qq) & 1u) ? (uni(nb[qq].count) + 7) & -8 : 0;
+            const int c = want && ((any >> qq) & 1u) ? (uni(sc[qq]) + 7) & -8 : 0;
             if (want && npts + c <= TILE_PTS) {
                 npts += c;
                 take = qq + 1;
@@ -840,11 +875,24 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
         for (int qq = 0; qq < SB; ++qq) {
             if (qq < take && o_r[qq + 1] > o_r[qq]) {
                 const int cnt = uni(nb[qq].count), st = uni(nb[qq].start);
+                const int nsc = uni(sc[qq]);
                 const int size = o_r[qq + 1] - o_r[qq];
-                const bool real = lane < cnt;
-                float4 p = make_float4(INFINITY, INFINITY, INFINITY, __int_as_float(-1));
+                const float4 filler = make_float4(INFINITY, INFINITY, INFINITY, __int_as_float(-1));
+                float4 p = filler;
+                bool real = lane < cnt;
                 if (real) p = pts[st + lane];
-                if (lane < size) tile[tslot(o_r[qq] + lane)] = p;
+                if (types) {
+                    // only the source points, packed at the front
+                    real = real && __float_as_int(p.w) < src_hi;
+                    const uint64_t rm = __ballot(real);
+                    if (real) tile[tslot(o_r[qq] + (int)__popcll(rm & lanemask_lt()))] = p;
+                    if (lane >= nsc && lane < size) tile[tslot(o_r[qq] + lane)] = filler;
+                    wave_lds_sync();
+                    real = lane < nsc;
+                    p = real ? tile[tslot(o_r[qq] + lane)] : filler;
+                } else if (lane < size) {
+                    tile[tslot(o_r[qq] + lane)] = p;
+                }
                 float lx = real ? p.x : INFINITY, ly = real ? p.y : INFINITY,
                       lz = real ? p.z : INFINITY;
                 float hx = real ? p.x : -INFINITY, hy = real ? p.y : -INFINITY,
@@ -858,7 +906,7 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
                 if ((lane & 7) == 0 && lane < size) {
                     // the chunk's box, and in lo.w its number of real points
                     float4 *bx = cbox + ((o_r[qq] + lane) >> 3) * 2;
-                    bx[0] = make_float4(lx, ly, lz, __int_as_float(min(8, max(0, cnt - lane))));
+                    bx[0] = make_float4(lx, ly, lz, __int_as_float(min(8, max(0, nsc - lane))));
                     bx[1] = make_float4(hx, hy, hz, 0.0f);
                 }
             }
@@ -894,7 +942,7 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
                         merge_chunk<K, C>(best, ch);
                         steps += (unsigned)((min(f1, j0 + C * SS) - j0) / SS);
                     }
-                    const int cnt = uni(nb[0].count);
+                    const int cnt = uni(sc[0]);
                     if (act) evals += cnt > h ? (unsigned)((cnt - h + SS - 1) / SS) : 0u;
                 }
                 return;
@@ -995,7 +1043,7 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
 
 typedef void (*leaf_fn)(const int2 *, int2 *, const Node *, const float4 *, int, const int *,
                         int32_t *, float *, unsigned long long *, const unsigned long long *, int,
-                        int, int, int, int);
+                        int, int, int, int, const int *, int, int);
 
 template <int K>
 leaf_fn leaf_ptr() {
@@ -1037,6 +1085,8 @@ jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s,
                   const AllocCtx *scratch) {
     const AllocCtx *ac = scratch ? scratch : &t->ac;
     const int P = t->P;
+    // a joint tree of source and query points: rows are the query points
+    const bool joint = t->n_src >= 0;
     for (int p = 0; p <= JZ_MAX_PLANES; ++p) t->st.list_entries[p] = 0;
     t->st.leaf_pairs = t->st.leaf_pairs_visited = 0;
     t->st.evaluations = 0;
@@ -1126,12 +1176,11 @@ jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s,
             k_walk_items<<<(unsigned)((n_par + 63) / 64), 64, 0, s>>>(
                 par_spl, (int)n_par, cb_of(p), d_items.as<int2>(), n_items);
             k_knn_step<<<blocks_for(item_bound(p), WPB), 64 * WPB, 0, s>>>(
-                d_items.as<int2>(), n_items, cb_of(p), seg_in, list_in, par_spl, t->nodes[p].as<Node>(), k,
-                                                            segs[p].as<int2>(), lists[p].as<int2>(),
-                                                            ctr + (size_t)p * LIST_ARENAS,
-                                                            cap[p] / LIST_ARENAS, ctr + CTR_FLAG,
-                                                            top ? LCAP : walk_cap,
-                                                            top ? 0 : sort_max);
+                d_items.as<int2>(), n_items, cb_of(p), seg_in, list_in, par_spl,
+                t->nodes[p].as<Node>(), k, segs[p].as<int2>(), lists[p].as<int2>(),
+                ctr + (size_t)p * LIST_ARENAS, cap[p] / LIST_ARENAS, ctr + CTR_FLAG,
+                top ? LCAP : walk_cap, top ? 0 : sort_max,
+                joint ? t->src_cnt[p].as<int>() : nullptr);
         }
         presort(lists[0].as<int2>(), segs[0].as<int2>(), t->L[0], leaf_cap,
                 ctr + c_long + 2 * JZ_MAX_PLANES);
@@ -1146,7 +1195,8 @@ jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s,
                 segs[0].as<int2>(), lists[0].as<int2>(), t->nodes[0].as<Node>(),
                 t->pts4.as<float4>(), (int)t->L[0], t->nsets > 1 ? t->leaf_base.as<int>() : nullptr,
                 idx, dist2, ctr + CTR_STATS, ctr + CTR_FLAG, leaf_cap, sort_max, k, col,
-                std::min(32, k - col));
+                std::min(32, k - col), joint ? t->src_cnt[0].as<int>() : nullptr,
+                joint ? (int)t->n_src : INT_MAX, joint ? (int)t->n_src : 0);
             JZ_HIP(hipGetLastError());
         }
         if (ev.on) JZ_HIP(hipEventRecord(ev[2], s));

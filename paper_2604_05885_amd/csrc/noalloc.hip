@@ -67,6 +67,7 @@ void bump_free(void *ctx, void *p, size_t bytes, void *) {
 extern "C" JZ_API jz_status jz_knn_noalloc(jz_tree *t, int k, int32_t *idx, float *dist2,
                                            void *stream) {
     if (!t) return jz_fail(JZ_E_INVALID, "tree is NULL");
+    if (t->n_src >= 0) return jz_fail(JZ_E_INVALID, "a joint tree takes jz_knn_query");
     if (k < 1) return jz_fail(JZ_E_INVALID, "k must be >= 1");
     if (k > JZ_MAX_K) return jz_fail(JZ_E_UNSUPPORTED, "k > %d is not supported", JZ_MAX_K);
     if (t->n > 0 && (!idx || !dist2)) return jz_fail(JZ_E_INVALID, "output is NULL");

@@ -24,6 +24,7 @@ import numpy as np
 __all__ = [
     "uniform",
     "clustered",
+    "clump_params",
     "clustered_device",
     "lattice",
     "linking_length",
@@ -117,48 +118,51 @@ def lattice(m: int, spacing_log2: int = -4, offset=(0, 0, 0)) -> np.ndarray:
     return np.ascontiguousarray(out)
 
 
-def clustered_device(n: int, clumps: int, seed: int, device="cuda", *,
-                     frac_clumped: float = 0.6, sigma_range=(0.002, 0.02), slope: float = -1.9,
-                     wmax: float = 1.0e4, stream=None):
-    """The recipe of :func:`clustered`, drawn on the GPU with torch (for request
-    streams too large to pre-generate on the host).
-
-    The per-clump parameters (centres, sigmas, member counts) come from numpy
-    exactly as in :func:`clustered`; the member offsets, the background and the
-    shuffle are drawn with a torch generator seeded by ``seed`` on ``device``,
-    so the values differ from :func:`clustered` for the same seed while the
-    distribution is the same. Returns a float32 (n, 3) tensor, enqueued on
-    ``stream`` (default: the current stream).
-    """
-    import torch
+def clump_params(n: int, clumps: int, seed: int, *, frac_clumped: float = 0.6,
+                 sigma_range=(0.002, 0.02), slope: float = -1.9, wmax: float = 1.0e4):
+    """The per-clump parameters of :func:`clustered` for one set: (number of
+    clumped points, centres [C, 3], sigmas [C], member counts [C]), drawn with
+    numpy exactly as :func:`clustered` draws them."""
     rng = np.random.default_rng(seed)
     n_cl = int(round(frac_clumped * n)) if clumps > 0 else 0
     clumps = max(int(clumps), 1)
     centres = rng.random((clumps, 3))
     sig = np.exp(rng.uniform(math.log(sigma_range[0]), math.log(sigma_range[1]), clumps))
     w = _power_law_weights(rng, clumps, slope, 1.0, wmax)
-    counts = _apportion(n_cl, w)
-    ctx = torch.cuda.stream(stream) if stream is not None else torch.cuda.stream(
-        torch.cuda.current_stream())
-    with ctx:
-        g = torch.Generator(device=device)
-        g.manual_seed(int(seed) & 0x7FFFFFFFFFFFFFFF)
-        pts = torch.empty((n, 3), dtype=torch.float64, device=device)
-        if n_cl:
-            owner = torch.repeat_interleave(torch.arange(clumps, device=device),
-                                            torch.from_numpy(counts).to(device),
-                                            output_size=n_cl)
-            c = torch.from_numpy(centres).to(device)
-            sg = torch.from_numpy(sig).to(device)
-            off = torch.randn((n_cl, 3), generator=g, dtype=torch.float64, device=device)
-            pts[:n_cl] = torch.remainder(c[owner] + sg[owner, None] * off, 1.0)
-        if n > n_cl:
-            pts[n_cl:] = torch.rand((n - n_cl, 3), generator=g, dtype=torch.float64,
-                                    device=device)
-        perm = torch.randperm(n, generator=g, device=device)
-        out = pts[perm].to(torch.float32)
-        return torch.where(out >= 1.0, torch.zeros((), dtype=out.dtype, device=device),
-                           out).contiguous()
+    return n_cl, centres, sig, _apportion(n_cl, w)
+
+
+def clustered_device(n: int, seed: int, n_cl: int, centres, sig, counts, device="cuda"):
+    """The recipe of :func:`clustered`, drawn on the GPU with torch on the
+    current stream, for request streams too large to pre-generate.
+
+    ``centres`` / ``sig`` / ``counts`` are device tensors of one set's clump
+    parameters (:func:`clump_params`); the member offsets and the background
+    are drawn with a torch generator seeded by ``seed``, and the input order
+    is a random affine permutation i -> (a i + c) mod n (a coprime to n)
+    instead of a full shuffle, so the values differ from :func:`clustered`
+    for the same seed while the distribution is the same. Returns a float32
+    (n, 3) tensor; no call waits for the device.
+    """
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed) & 0x7FFFFFFFFFFFFFFF)
+    pts = torch.empty((n, 3), dtype=torch.float64, device=device)
+    if n_cl:
+        owner = torch.repeat_interleave(torch.arange(centres.shape[0], device=device), counts,
+                                        output_size=n_cl)
+        off = torch.randn((n_cl, 3), generator=g, dtype=torch.float64, device=device)
+        pts[:n_cl] = torch.remainder(centres[owner] + sig[owner, None] * off, 1.0)
+    if n > n_cl:
+        pts[n_cl:] = torch.rand((n - n_cl, 3), generator=g, dtype=torch.float64, device=device)
+    rng = np.random.default_rng(int(seed) ^ 0x5EED)
+    a = int(rng.integers(1, max(2, n)))
+    while math.gcd(a, n) != 1:
+        a += 1
+    c = int(rng.integers(0, max(1, n)))
+    perm = torch.remainder(torch.arange(n, device=device, dtype=torch.int64) * a + c, n)
+    out = pts[perm].to(torch.float32)
+    return torch.where(out >= 1.0, torch.zeros((), dtype=out.dtype, device=device), out)
 
 
 def linking_length(n: int, alpha: float = 0.2, volume: float = 1.0) -> float:

@@ -491,3 +491,110 @@ def test_catalogue_singletons_and_min_members():
     assert np.array_equal(cat["first"], np.arange(300)) and np.all(cat["count"] == 1)
     assert np.array_equal(cat["cm"], p.astype(np.float64)) and np.all(cat["r_inertia"] == 0)
     assert oracle.fof_catalogue(p, lab, min_members=2)["count"].size == 0
+
+
+# ---------------------------------------------------------------- separate query and source sets
+
+def test_cross_knn_equals_self_knn_when_queries_are_the_sources():
+    """Queries identical to the sources (same order): the cross kNN is the
+    self kNN, computed by a separate code path."""
+    for name, p in point_sets(4, 400):
+        for k in (1, 9, 32):
+            i1, d1 = oracle.knn_bf(p, k)
+            i2, d2 = oracle.knn_cross_bf(p, p, k)
+            assert np.array_equal(i1, i2) and np.array_equal(d1.view(np.uint32), d2.view(np.uint32))
+
+
+def test_cross_knn_lattice_cell_centres():
+    """A query at the centre of a lattice cell (spacing a, all exact in f32)
+    sees the shells r^2/a^2 = 3/4 (8 corners), 11/4 (24), 19/4 (24), 27/4
+    (32) of an interior cell, ties in source index order."""
+    p = inputs.lattice(8)
+    a = 2.0 ** -4
+    q = np.array([[3.5 * a, 3.5 * a, 3.5 * a], [4.5 * a, 2.5 * a, 3.5 * a]], dtype=np.float32)
+    idx, d2 = oracle.knn_cross_bf(p, q, 88)
+    shells = np.repeat([3, 11, 19, 27], [8, 24, 24, 32]) / 4.0 * a * a
+    for r in range(2):
+        assert np.array_equal(d2[r], shells.astype(np.float32))
+        for lo, hi in ((0, 8), (8, 32), (32, 56), (56, 88)):
+            assert np.all(np.diff(idx[r, lo:hi]) > 0)
+
+
+def test_cross_kd_equals_bf():
+    rng = np.random.default_rng(12)
+    for seed in range(6):
+        ns, nq = int(rng.integers(1, 3000)), int(rng.integers(1, 2000))
+        s = inputs.clustered(ns, max(1, ns // 64), seed)
+        q = inputs.clustered(nq, max(1, nq // 64), seed + 50)
+        for k in (1, 16, 40):
+            i1, d1 = oracle.knn_cross_bf(s, q, k)
+            i2, d2 = oracle.knn_cross_kd(s, q, k)
+            assert np.array_equal(i1, i2) and np.array_equal(d1.view(np.uint32), d2.view(np.uint32))
+
+
+# ---------------------------------------------------------------- periodic box
+
+def test_periodic_lattice_every_row_has_the_interior_shells():
+    """An 8^3 lattice of spacing a filling the periodic box L = 8a: by
+    periodicity every point, also on the faces, sees the shells
+    r^2/a^2 = 0, 1, 2, 3, 4, 5, 6, 8, 9 of sizes 1, 6, 12, 8, 6, 24, 24, 12,
+    30 (123 points within offsets of 3 < L/2), ties in index order."""
+    a = 2.0 ** -4
+    p = inputs.lattice(8)
+    L = 8 * a
+    idx, d2 = oracle.knn_bf_periodic(p, L, 123)
+    shells = (np.repeat([0, 1, 2, 3, 4, 5, 6, 8, 9], [1, 6, 12, 8, 6, 24, 24, 12, 30]) *
+              np.float32(a * a)).astype(np.float32)
+    assert np.all(d2 == shells[None, :])
+    starts = np.cumsum([0, 1, 6, 12, 8, 6, 24, 24, 12])
+    ends = np.cumsum([1, 6, 12, 8, 6, 24, 24, 12, 30])
+    for s, e in zip(starts, ends):
+        assert np.all(np.diff(idx[:, s:e], axis=1) > 0)
+    # the open box differs at the faces: a corner point has only 3 neighbours at a
+    _, d2o = oracle.knn_bf(p, 7)
+    assert np.count_nonzero(d2o[0] == np.float32(a * a)) == 3
+
+
+def test_periodic_fof_lattice_and_a_pair_across_the_boundary():
+    a = 2.0 ** -4
+    p = inputs.lattice(8)
+    L = 8 * a
+    assert np.all(oracle.fof_bf_periodic(p, L, a) == 0)
+    assert np.array_equal(oracle.fof_bf_periodic(p, L, np.nextafter(np.float32(a), 0)),
+                          np.arange(p.shape[0]))
+    q = np.array([[0.01, 0.5, 0.5], [0.99, 0.5, 0.5], [0.5, 0.5, 0.5]], dtype=np.float32)
+    assert oracle.fof_bf_periodic(q, 1.0, 0.03).tolist() == [0, 0, 2]
+    assert oracle.fof_bf(q, 0.03).tolist() == [0, 1, 2]
+    d = oracle.dist2_f32_periodic(q[0], q[1], 1.0)
+    dx = np.float32(np.float32(0.01) - np.float32(0.99)) + np.float32(1.0)
+    assert d == dx * dx
+
+
+def test_periodic_equals_open_without_wraps():
+    """Every coordinate difference below half the period: no difference
+    wraps, so the periodic results are the open ones bit for bit."""
+    p = (inputs.clustered(2000, 8, 3) * np.float32(0.3)).astype(np.float32)
+    i1, d1 = oracle.knn_bf(p, 16)
+    i2, d2 = oracle.knn_bf_periodic(p, 1.0, 16)
+    assert np.array_equal(i1, i2) and np.array_equal(d1.view(np.uint32), d2.view(np.uint32))
+    b = inputs.linking_length(2000, 0.3) * 0.3
+    assert np.array_equal(oracle.fof_bf(p, b), oracle.fof_bf_periodic(p, 1.0, b))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_periodic_kd_equals_bf(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(1, 3000))
+    L = float(np.float32(rng.choice([1.0, 0.75, 3.0])))
+    # clumps pushed against faces and corners so that wraps matter
+    p = inputs.clustered(n, max(1, n // 64), seed)
+    p = np.where(rng.random(p.shape) < 0.5, p * np.float32(0.05), np.float32(1) - p * np.float32(0.05))
+    p = (p.astype(np.float32) * np.float32(L)).astype(np.float32)
+    p[p >= np.float32(L)] = 0.0
+    for k in (1, 16, 40):
+        i1, d1 = oracle.knn_bf_periodic(p, L, k)
+        i2, d2 = oracle.knn_kd_periodic(p, L, k)
+        assert np.array_equal(i1, i2) and np.array_equal(d1.view(np.uint32), d2.view(np.uint32)), k
+    for alpha in (0.2, 0.7):
+        b = inputs.linking_length(max(n, 1), alpha) * L
+        assert np.array_equal(oracle.fof_bf_periodic(p, L, b), oracle.fof_kd_periodic(p, L, b))
