@@ -44,6 +44,10 @@ def parse():
     ap.add_argument("--k", type=int, default=16)
     ap.add_argument("--alpha", type=float, default=0.2)
     ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--period", type=float, default=0.0,
+                    help="step mode: > 0 runs in the periodic cube [0, period)^3 (minimum image)")
+    ap.add_argument("--key-bits", type=int, default=0,
+                    help="step mode: Morton key bits per dimension (0: the library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "leaf_knn_traffic.json"),
@@ -90,11 +94,17 @@ def main():
     d2 = torch.empty((n, k), dtype=torch.float32, device="cuda")
     lab = torch.empty(n, dtype=torch.int32, device="cuda")
     stream = torch.cuda.current_stream()
+    kw = {}
+    if args.period > 0:
+        kw["period"] = args.period
+    if args.key_bits > 0:
+        kw["key_bits"] = args.key_bits
+    opts = api.default_opts(**kw) if kw else None
 
     def step(ev=None):
         if ev is not None:
             ev[0].record(stream)
-        t = api.jz_build(dev, stream=stream)
+        t = api.jz_build(dev, opts, stream=stream)
         if ev is not None:
             ev[1].record(stream)
         t.knn(k, idx, d2, stream=stream)
@@ -155,7 +165,8 @@ def main():
         "config": {"workload": "clustered N=2^24 f32 in [0,1)^3, 60%% in %d Gaussian clumps "
                                "(sigma 0.002-0.02, counts ~ w^-1.9) + 40%% uniform; "
                                "kNN k=%d + FoF b=%.4g (alpha=%g)" % (args.clumps, k, b, args.alpha),
-                   "n": n, "k": k, "b": b, "seed": args.seed, "max_clump": info["max_clump"]},
+                   "n": n, "k": k, "b": b, "seed": args.seed, "max_clump": info["max_clump"],
+                   "period": args.period},
         "roofline": {"bound": "alu", "kernel": "k_leaf_knn<16>", "achieved": achieved,
                      "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / VALU_PEAK_TFLOPS,
                      "traffic": traffic, "evaluations": evals, "flops_per_eval": FLOPS_PER_EVAL,
@@ -165,7 +176,9 @@ def main():
                       "fof_leaf_ms": float(np.mean([s["leaf_ms"] for _, s in per])),
                       "knn_stats": sk, "fof_stats": sf},
     }
-    if not args.no_cpu_baseline:
+    if args.period > 0:
+        out["config"]["workload"] += "; periodic cube of side %g (minimum image)" % args.period
+    if not args.no_cpu_baseline and args.period == 0:
         import oracle
         threads = args.cpu_threads or oracle.default_threads()
         t0 = time.perf_counter()

@@ -83,6 +83,20 @@ typedef struct jz_build_opts {
                               walked (so the walk can stop at the first entry beyond its
                               radius); longer lists are read unordered. Default 8192, range
                               [256, 8192]. */
+    float period;          /* > 0: the points lie in the periodic cube [0, period)^3 (coordinates
+                              outside it: JZ_E_INVALID) and kNN / FoF use the minimum-image
+                              distance: each coordinate difference dx = fl(x_i - x_j) becomes
+                              fl(dx - period) if dx > fl(period / 2) and fl(dx + period) if
+                              dx < -fl(period / 2), then the fixed dist2 expression. The paper's
+                              periodic cosmological case. 0 (default): open space. */
+    float reg_fmax;        /* > 0: regularization (paper: section on regularization) with
+                              f_max = reg_fmax (the paper uses about 50): on every plane, nodes
+                              may not exceed f_max times V90, the point-weighted mean volume of
+                              the smallest nodes holding 90% of the points, so gaps whose level
+                              (volume 2^level of the Morton cell spanning them) exceeds
+                              log2(f_max V90) are split as well. Keeps a few points far from the
+                              bulk out of huge nodes. 0 (default): off. Results never depend
+                              on it. */
 } jz_build_opts;
 
 /* Fill *o with the defaults above. */
@@ -119,8 +133,9 @@ JZ_API jz_status jz_knn(jz_tree *t, int k, int32_t *idx, float *dist2, void *str
  * before the z-order sort, so the hierarchy adapts to both distributions,
  * and every node records how many source points it holds. Nodes are split on
  * the combined count (at most leaf_max points of both types together per
- * leaf). Errors as jz_build. Such a tree takes jz_knn_query only (jz_knn,
- * jz_fof and the catalogue return JZ_E_INVALID on it). */
+ * leaf). Errors as jz_build; a periodic box (opts->period > 0) is not
+ * supported here (JZ_E_UNSUPPORTED). Such a tree takes jz_knn_query only
+ * (jz_knn, jz_fof and the catalogue return JZ_E_INVALID on it). */
 JZ_API jz_status jz_build_joint(const float *sources, int64_t n_src, const float *queries,
                                 int64_t n_qry, void *stream, const jz_build_opts *opts,
                                 const jz_allocator *alloc, jz_tree **out);
@@ -199,7 +214,8 @@ typedef struct jz_group {
     double r_inertia;   /* inertia radius: RMS distance of the members from cm */
 } jz_group;
 
-/* On a tree from jz_build (one set): label[n] (DEVICE, may be NULL) receives
+/* On a tree from jz_build (one set, open space: a periodic tree returns
+ * JZ_E_INVALID): label[n] (DEVICE, may be NULL) receives
  * the labels as jz_fof gives them; order[n] (DEVICE) the input indices in
  * group order; groups[max_groups] (DEVICE) the groups with >= min_members
  * (>= 1) points, in label order; *ngroups (HOST) their number. vel: DEVICE

@@ -40,7 +40,8 @@ class BuildOpts(ctypes.Structure):
     _fields_ = [("leaf_max", ctypes.c_int), ("coarsen", ctypes.c_int), ("n_target", ctypes.c_int),
                 ("ngr", ctypes.c_int), ("key_bits", ctypes.c_int),
                 ("list_per_node", ctypes.c_float), ("auto_regrow", ctypes.c_int),
-                ("keep_keys", ctypes.c_int), ("sort_max", ctypes.c_int)]
+                ("keep_keys", ctypes.c_int), ("sort_max", ctypes.c_int),
+                ("period", ctypes.c_float), ("reg_fmax", ctypes.c_float)]
 
 
 class Stats(ctypes.Structure):

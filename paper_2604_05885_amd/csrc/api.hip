@@ -235,6 +235,10 @@ jz_status check_opts(const jz_build_opts &o) {
         return jz_fail(JZ_E_INVALID, "list_per_node must be finite and >= 1");
     if (o.sort_max < 256 || o.sort_max > 8192)
         return jz_fail(JZ_E_INVALID, "sort_max must be in [256, 8192]");
+    if (!(o.period >= 0.0f) || !std::isfinite(o.period))
+        return jz_fail(JZ_E_INVALID, "period must be finite and >= 0");
+    if (!(o.reg_fmax >= 0.0f) || !std::isfinite(o.reg_fmax))
+        return jz_fail(JZ_E_INVALID, "reg_fmax must be finite and >= 0");
     return JZ_OK;
 }
 
@@ -310,6 +314,8 @@ void jz_default_opts(jz_build_opts *o) {
     o->auto_regrow = 1;
     o->keep_keys = 0;
     o->sort_max = 8192;
+    o->period = 0.0f;
+    o->reg_fmax = 0.0f;
 }
 
 jz_status jz_build(const float *points, int64_t n, void *stream, const jz_build_opts *opts,
@@ -343,6 +349,8 @@ jz_status jz_build_joint(const float *sources, int64_t n_src, const float *queri
         return jz_fail(JZ_E_INVALID, "points are NULL");
     if (alloc && (!alloc->alloc || !alloc->free))
         return jz_fail(JZ_E_INVALID, "allocator needs both alloc and free");
+    if (opts && opts->period != 0.0f)
+        return jz_fail(JZ_E_UNSUPPORTED, "a joint tree takes open space (period 0)");
     const int64_t n = n_src + n_qry;
     hipStream_t s = (hipStream_t)stream;
     AllocCtx ac;

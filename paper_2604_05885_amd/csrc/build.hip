@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <cmath>
 #include <cstring>
 #include <vector>
 
@@ -456,12 +457,14 @@ __global__ __launch_bounds__(256) void k_split_sizes(const uint64_t *__restrict_
                                                      int bits3, int has_sets,
                                                      const int *__restrict__ spl0,
                                                      const int *__restrict__ cnt0, int gallop0,
-                                                     int *__restrict__ nsz) {
+                                                     int *__restrict__ nsz,
+                                                     uint8_t *__restrict__ slv) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t m = *cnt0;  // L0 + 1 entries
     if (s >= m) return;
     const int64_t g = spl0[s];
     const int lv = gap_level(keys, n, g, bits3, has_sets);
+    slv[s] = (uint8_t)lv;
     if (lv >= kBoundaryLevel) {
         nsz[s] = INT_MAX;
         return;
@@ -512,6 +515,7 @@ __global__ __launch_bounds__(256) void k_split_sizes(const uint64_t *__restrict_
 __global__ __launch_bounds__(256) void k_plane_flags(const int *__restrict__ lsi_prev,
                                                      const int *__restrict__ cnt_prev,
                                                      const int *__restrict__ nsz, int64_t nmax,
+                                                     const uint8_t *__restrict__ slv, int lvl_max,
                                                      uint8_t *__restrict__ flags,
                                                      int *__restrict__ blk_cnt) {
     __shared__ int s_c[4];
@@ -521,8 +525,52 @@ __global__ __launch_bounds__(256) void k_plane_flags(const int *__restrict__ lsi
     for (int t = threadIdx.x; t < LF_TILE; t += blockDim.x) {
         const int64_t j = base + t;
         if (j >= m) break;
-        const uint8_t f = (j == 0 || j == m - 1 || (int64_t)nsz[lsi_prev[j]] > nmax) ? 1 : 0;
+        const int ls = lsi_prev[j];
+        const uint8_t f = (j == 0 || j == m - 1 || (int64_t)nsz[ls] > nmax ||
+                           (int)slv[ls] > lvl_max) ? 1 : 0;
         flags[j] = f;
+        cnt += f;
+    }
+    cnt = wave_sum(cnt);
+    if (lane_id() == 0) s_c[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) blk_cnt[blockIdx.x] = s_c[0] + s_c[1] + s_c[2] + s_c[3];
+}
+
+// Regularization (paper: section on regularization): points per node level
+// over the nodes of a plane. Node i spans the sorted points between leaf
+// splits lsi[i] and lsi[i + 1] (lsi = NULL: the leaf plane itself); its level
+// is that of its first and last point (the largest gap level inside it).
+__global__ __launch_bounds__(256) void k_level_hist(const uint64_t *__restrict__ keys,
+                                                    const int *__restrict__ spl0,
+                                                    const int *__restrict__ lsi,
+                                                    const int *__restrict__ cnt, int bits3,
+                                                    int has_sets,
+                                                    unsigned long long *__restrict__ hist) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i + 1 >= *cnt) return;
+    const int64_t a = spl0[lsi ? lsi[i] : i], e = spl0[lsi ? lsi[i + 1] : i + 1];
+    const int lv = e - a > 1 ? pair_level(keys, a, e - 1, bits3, has_sets) : 0;
+    atomicAdd(hist + lv, (unsigned long long)(e - a));
+}
+
+// leaf plane: also split every gap whose level exceeds lvl_max; per-block
+// counts as k_leaf_flags
+__global__ __launch_bounds__(256) void k_reg_leaf_flags(const uint64_t *__restrict__ keys,
+                                                        int64_t n, int bits3, int has_sets,
+                                                        int lvl_max, uint8_t *__restrict__ flags,
+                                                        int *__restrict__ blk_cnt) {
+    __shared__ int s_c[4];
+    int cnt = 0;
+    const int64_t g0 = (int64_t)blockIdx.x * LF_TILE;
+    for (int t = threadIdx.x; t < LF_TILE; t += blockDim.x) {
+        const int64_t g = g0 + t;
+        if (g > n) break;
+        uint8_t f = flags[g];
+        if (!f && gap_level(keys, n, g, bits3, has_sets) > lvl_max) {
+            f = 1;
+            flags[g] = 1;
+        }
         cnt += f;
     }
     cnt = wave_sum(cnt);
@@ -703,6 +751,23 @@ jz_status source_counts(jz_tree *t, hipStream_t s) {
     return JZ_OK;
 }
 
+// Regularization: the largest node level of a plane from its histogram of
+// points per node level. V90 is the point-weighted mean volume (2^level) of
+// the smallest nodes that together hold 90% of the points; nodes may not
+// exceed f_max * V90, i.e. levels above floor(log2(f_max * V90)) are split.
+static int reg_level_max(const unsigned long long *hist, double f_max) {
+    double total = 0;
+    for (int l = 0; l < 256; ++l) total += (double)hist[l];
+    if (total <= 0) return 1000;
+    double cum = 0, wsum = 0;
+    for (int l = 0; l < 256 && cum < 0.9 * total; ++l) {
+        cum += (double)hist[l];
+        wsum += (double)hist[l] * std::ldexp(1.0, l);
+    }
+    const double v90 = wsum / cum;
+    return (int)std::floor(std::log2(f_max * v90));
+}
+
 static int plan_planes(int64_t n, const jz_build_opts &o) {
     int P = 1;
     double nmax = (double)o.leaf_max;
@@ -785,21 +850,61 @@ jz_status build_tree(jz_tree *t, const float *points, hipStream_t s) {
     k_compact<<<nb, 256, 0, s>>>(d_flags.as<uint8_t>(), ngaps, nullptr, d_boff.as<int>(),
                                  t->spl[0].as<int>(), nullptr, nullptr);
     JZ_HIP(hipGetLastError());
-    int host_hdr[2];
+    // regularization: the largest level each plane's nodes may have
+    const bool reg = o.reg_fmax > 0.0f;
+    DBuf d_hist2;
+    int lvl_max = 1000;
+    auto plane_level_max = [&](const int *lsi, const int *cnt_dev) -> jz_status {
+        JZ_TRY(zero_words(d_hist2.as<unsigned long long>(), 256, s));
+        k_level_hist<<<blocks_for(ngaps, 256), 256, 0, s>>>(keys, t->spl[0].as<int>(), lsi,
+                                                            cnt_dev, bits3, has_sets,
+                                                            d_hist2.as<unsigned long long>());
+        unsigned long long h[256];
+        JZ_HIP(hipMemcpyAsync(h, d_hist2.p, sizeof(h), hipMemcpyDeviceToHost, s));
+        JZ_HIP(hipStreamSynchronize(s));
+        lvl_max = std::max(lvl_max == 1000 ? 0 : lvl_max, reg_level_max(h, o.reg_fmax));
+        return JZ_OK;
+    };
+    if (reg) {
+        JZ_TRY(d_hist2.get(ac, 256 * sizeof(unsigned long long), s));
+        JZ_TRY(plane_level_max(nullptr, cnts + 0));
+        k_reg_leaf_flags<<<nb, 256, 0, s>>>(keys, n, bits3, has_sets, lvl_max,
+                                            d_flags.as<uint8_t>(), d_bcnt.as<int>());
+        k_scan_counts<<<1, 1024, 0, s>>>(d_bcnt.as<int>(), (int)nb, d_boff.as<int>(), cnts + 0);
+        k_compact<<<nb, 256, 0, s>>>(d_flags.as<uint8_t>(), ngaps, nullptr, d_boff.as<int>(),
+                                     t->spl[0].as<int>(), nullptr, nullptr);
+        JZ_HIP(hipGetLastError());
+    }
+    int host_hdr[8];
     JZ_HIP(hipMemcpyAsync(host_hdr, cnts, sizeof(int), hipMemcpyDeviceToHost, s));
-    JZ_HIP(hipMemcpyAsync(host_hdr + 1, d_bbox.as<int>() + 6, sizeof(int), hipMemcpyDeviceToHost,
+    JZ_HIP(hipMemcpyAsync(host_hdr + 1, d_bbox.as<int>(), 7 * sizeof(int), hipMemcpyDeviceToHost,
                           s));
     JZ_HIP(hipStreamSynchronize(s));
-    if (host_hdr[1]) return jz_fail(JZ_E_NONFINITE, "input contains NaN or infinite coordinates");
+    if (host_hdr[7]) return jz_fail(JZ_E_NONFINITE, "input contains NaN or infinite coordinates");
+    if (o.period > 0.0f) {
+        // the periodic cube is [0, period)^3
+        auto of = [](int v) {
+            const int i = v >= 0 ? v : v ^ 0x7FFFFFFF;
+            float f;
+            std::memcpy(&f, &i, sizeof(f));
+            return f;
+        };
+        for (int a = 0; a < 3; ++a)
+            if (!(of(host_hdr[1 + a]) >= 0.0f) || !(of(host_hdr[4 + a]) < o.period))
+                return jz_fail(JZ_E_INVALID, "with period %g every coordinate must lie in "
+                               "[0, %g)", (double)o.period, (double)o.period);
+    }
     const int64_t m0 = host_hdr[0];  // L0 + 1
     t->L[0] = m0 - 1;
 
     // 6-7: node sizes at leaf splits, coarser planes
     const int P = plan_planes(n, o);
-    DBuf d_nsz, lsiA, lsiB;
+    DBuf d_nsz, d_slv, lsiA, lsiB;
     JZ_TRY(d_nsz.get(ac, m0 * sizeof(int), s));
+    JZ_TRY(d_slv.get(ac, m0, s));
     k_split_sizes<<<blocks_for(m0, 256), 256, 0, s>>>(keys, n, bits3, has_sets, t->spl[0].as<int>(),
-                                                     cnts + 0, o.leaf_max, d_nsz.as<int>());
+                                                     cnts + 0, o.leaf_max, d_nsz.as<int>(),
+                                                     d_slv.as<uint8_t>());
     if (P > 1) {
         JZ_TRY(lsiA.get(ac, m0 * sizeof(int), s));
         JZ_TRY(lsiB.get(ac, m0 * sizeof(int), s));
@@ -809,13 +914,20 @@ jz_status build_tree(jz_tree *t, const float *points, hipStream_t s) {
         for (int p = 1; p < P; ++p) {
             nmax *= o.coarsen;
             JZ_TRY(t->spl[p].get(ac, m0 * sizeof(int), s));
-            k_plane_flags<<<nbp, 256, 0, s>>>(lsiA.as<int>(), cnts + p - 1, d_nsz.as<int>(), nmax,
-                                              d_flags.as<uint8_t>(), d_bcnt.as<int>());
-            k_scan_counts<<<1, 1024, 0, s>>>(d_bcnt.as<int>(), (int)nbp, d_boff.as<int>(),
-                                             cnts + p);
-            k_compact<<<nbp, 256, 0, s>>>(d_flags.as<uint8_t>(), m0, cnts + p - 1,
-                                          d_boff.as<int>(), t->spl[p].as<int>(), lsiA.as<int>(),
-                                          lsiB.as<int>());
+            // with regularization a plane is selected twice: by counts, then
+            // also splitting the levels above its nodes' lvl_max
+            for (int pass = 0; pass < (reg ? 2 : 1); ++pass) {
+                k_plane_flags<<<nbp, 256, 0, s>>>(lsiA.as<int>(), cnts + p - 1, d_nsz.as<int>(),
+                                                  nmax, d_slv.as<uint8_t>(),
+                                                  pass ? lvl_max : 1000, d_flags.as<uint8_t>(),
+                                                  d_bcnt.as<int>());
+                k_scan_counts<<<1, 1024, 0, s>>>(d_bcnt.as<int>(), (int)nbp, d_boff.as<int>(),
+                                                 cnts + p);
+                k_compact<<<nbp, 256, 0, s>>>(d_flags.as<uint8_t>(), m0, cnts + p - 1,
+                                              d_boff.as<int>(), t->spl[p].as<int>(),
+                                              lsiA.as<int>(), lsiB.as<int>());
+                if (reg && pass == 0) JZ_TRY(plane_level_max(lsiB.as<int>(), cnts + p));
+            }
             std::swap(lsiA.p, lsiB.p);
         }
         JZ_HIP(hipGetLastError());

@@ -237,6 +237,9 @@ extern "C" JZ_API jz_status jz_fof_catalogue(jz_tree *t, float b, int min_member
     *ngroups = 0;
     if (t->nsets != 1 || t->n_src >= 0)
         return jz_fail(JZ_E_INVALID, "the catalogue takes a single-set tree from jz_build");
+    if (t->opts.period > 0.0f)
+        return jz_fail(JZ_E_INVALID, "the catalogue is for open space (a periodic group's centre "
+                       "of mass depends on how it is unwrapped)");
     if (!(b >= 0.0f) || !std::isfinite(b)) return jz_fail(JZ_E_INVALID, "b must be finite and >= 0");
     if (min_members < 1) return jz_fail(JZ_E_INVALID, "min_members must be >= 1");
     if (max_groups < 0 || (max_groups > 0 && !groups))

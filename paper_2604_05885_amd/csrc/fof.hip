@@ -42,11 +42,12 @@ __global__ void k_node_b2(const int *__restrict__ node_set, int64_t L,
 }
 
 // ParentToNode: one wave per parent, lanes over its children.
+template <bool PER>
 __global__ __launch_bounds__(64 * WPB) void k_fof_p2n(const int *__restrict__ par_spl,
                                                  const Node *__restrict__ nodes, int n_par,
                                                  const int *__restrict__ whole_par,
                                                  int *__restrict__ whole, int *__restrict__ uf,
-                                                 float b2, const float *__restrict__ b2n) {
+                                                 float b2, const float *__restrict__ b2n, float L) {
     const int w = WPB == 1 ? 0 : uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
     const int P = xcd_block(blockIdx.x, gridDim.x) * WPB + w;
     if (P >= n_par) return;
@@ -56,7 +57,7 @@ __global__ __launch_bounds__(64 * WPB) void k_fof_p2n(const int *__restrict__ pa
     for (int c = c0 + lane; c < c1; c += 64) {
         const Node me = nodes[c];
         const float bb = b2n ? b2n[c] : b2;
-        const int wc = (wp || box_up2(me, me) <= bb) ? 1 : 0;
+        const int wc = (wp || box_up2_m<PER>(me, me, L) <= bb) ? 1 : 0;
         whole[c] = wc;
         if (wp && c != c0) uf[me.start] = first;
     }
@@ -75,13 +76,14 @@ __global__ __launch_bounds__(64 * WPB) void k_fof_l2p(const Node *__restrict__ l
 
 enum PairCase { kDiscard = 0, kLinked = 1, kDescend = 2 };
 
+template <bool PER>
 __device__ __forceinline__ int fof_case(const Node &me, int c, const Node &o, int s, float bb,
-                                        int *whole, int *uf, bool do_link, float &lo) {
-    lo = box_low2(me, o);
+                                        int *whole, int *uf, bool do_link, float &lo, float L) {
+    lo = box_low2_m<PER>(me, o, L);
     if (lo > bb) return kDiscard;
     if (ld_acq(whole + c) && ld_acq(whole + s) && uf_find(uf, me.start) == uf_find(uf, o.start))
         return kDiscard;
-    if (box_up2(me, o) <= bb) {
+    if (box_up2_m<PER>(me, o, L) <= bb) {
         if (do_link) {
             uf_union(uf, me.start, o.start);
             st_rel(whole + c, 1);
@@ -96,12 +98,13 @@ __device__ __forceinline__ int fof_case(const Node &me, int c, const Node &o, in
 // Pass A links and counts the pairs to descend into; pass B re-evaluates and
 // writes them (the group state only merges between the passes, so pass B
 // emits a subset of what pass A counted; the segment length is what it wrote).
+template <bool PER>
 __global__ __launch_bounds__(64 * WPB) void k_fof_step(
     const int2 *__restrict__ seg_in, const int2 *__restrict__ list_in,
     const int *__restrict__ par_spl, const Node *__restrict__ nodes, int n_par, float b2,
     const float *__restrict__ b2n, int *__restrict__ whole, int *__restrict__ uf,
     int2 *__restrict__ seg_out, int2 *__restrict__ list_out,
-    unsigned long long *__restrict__ ctr, long long cap, unsigned long long *overflow) {
+    unsigned long long *__restrict__ ctr, long long cap, unsigned long long *overflow, float L) {
     __shared__ Node s_tile[WPB][64];
     const int w = WPB == 1 ? 0 : uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
     const int P = xcd_block(blockIdx.x, gridDim.x) * WPB + w;
@@ -128,7 +131,7 @@ __global__ __launch_bounds__(64 * WPB) void k_fof_step(
                     const int s = sb + j;
                     if (!act || s < c) continue;
                     float lo;
-                    if (fof_case(me, c, tile[j], s, bb, whole, uf, true, lo) == kDescend) ++cnt;
+                    if (fof_case<PER>(me, c, tile[j], s, bb, whole, uf, true, lo, L) == kDescend) ++cnt;
                 }
                 wave_lds_sync();
             }
@@ -161,7 +164,7 @@ __global__ __launch_bounds__(64 * WPB) void k_fof_step(
                     const int s = sb + j;
                     if (!act || s < c || emitted >= cnt) continue;
                     float lo;
-                    if (fof_case(me, c, tile[j], s, bb, whole, uf, false, lo) == kDescend) {
+                    if (fof_case<PER>(me, c, tile[j], s, bb, whole, uf, false, lo, L) == kDescend) {
                         list_out[pos + emitted] = make_int2(s, __float_as_int(lo));
                         ++emitted;
                     }
@@ -176,16 +179,10 @@ __global__ __launch_bounds__(64 * WPB) void k_fof_step(
 constexpr int FSB = 8;          // source leaves per batch
 constexpr int FTILE = 128;      // source points staged per batch
 
-__device__ __forceinline__ float point_box_low2_f(const float4 &q, const Node &b) {
-    const float gx = fmaxf(fmaxf(b.lo[0] - q.x, q.x - b.hi[0]), 0.0f);
-    const float gy = fmaxf(fmaxf(b.lo[1] - q.y, q.y - b.hi[1]), 0.0f);
-    const float gz = fmaxf(fmaxf(b.lo[2] - q.z, q.z - b.hi[2]), 0.0f);
-    const float xx = gx * gx;
-    const float yy = gy * gy;
-    const float zz = gz * gz;
-    const float s = xx + yy;
-    return s + zz;
-}
+// LDS slot of tile position j: permuted inside each chunk of 8 by the chunk's
+// low 3 bits (lanes reading the same position of different chunks spread
+// over the LDS banks)
+__device__ __forceinline__ int fslot(int j) { return j ^ ((j >> 3) & 7); }
 
 // Leaf stage: one wave per receiving leaf A, lanes over its points. Sources
 // (leaves B >= A) are read in batches of FSB Node records. A source is
@@ -199,11 +196,13 @@ __device__ __forceinline__ float point_box_low2_f(const float4 &q, const Node &b
 // parallel, and unions made where the roots differ (a lane's own root is
 // cached; groups only ever merge, so equal roots, even looked up at different
 // times, mean already connected). Two whole leaves need only one link.
+template <bool PER>
 __global__ __launch_bounds__(64 * WPB) void k_leaf_fof(
     const int2 *__restrict__ seg, const int2 *__restrict__ list, const Node *__restrict__ leaves,
     const float4 *__restrict__ pts, int n_leaves, float b2, const float *__restrict__ b2n,
     const int *__restrict__ whole, int *__restrict__ uf, unsigned long long *__restrict__ stats,
-    const unsigned long long *__restrict__ overflow) {
+    const unsigned long long *__restrict__ overflow, float L) {
+    const float Lh = 0.5f * L;
     __shared__ float4 s_tile[WPB][FTILE];
     __shared__ float4 s_box[WPB][FTILE / 8 * 2];  // (lo, hi) of every 8 tile positions
     __shared__ Node s_nodes[WPB][FSB];
@@ -247,7 +246,9 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_fof(
         wave_lds_sync();
         unsigned needbits = 0;
         for (int q = 0; q < nb_n; ++q)
-            if (!((skipmask >> q) & 1u) && act && point_box_low2_f(me, nb[q]) <= bb)
+            if (!((skipmask >> q) & 1u) && act &&
+                point_low2_m<PER>(me.x, me.y, me.z, nb[q].lo[0], nb[q].lo[1], nb[q].lo[2],
+                                  nb[q].hi[0], nb[q].hi[1], nb[q].hi[2], L) <= bb)
                 needbits |= 1u << q;
         const unsigned any = uni(wave_or(needbits));
         // take needed sources in order while their (8-padded) points fit
@@ -276,7 +277,7 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_fof(
                 const bool real = lane < cnt;
                 float4 p = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
                 if (real) p = pts[st + lane];
-                if (lane < size) tile[tslot(o_r[q] + lane)] = p;
+                if (lane < size) tile[fslot(o_r[q] + lane)] = p;
                 const float lx = group8_min(real ? p.x : INFINITY);
                 const float ly = group8_min(real ? p.y : INFINITY);
                 const float lz = group8_min(real ? p.z : INFINITY);
@@ -303,14 +304,9 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_fof(
         for (int c = 0; c < nch; ++c) {
             const float4 *bx = cbox + c * 2;
             const float4 blo = bx[0], bhi = bx[1];
-            const float gx = fmaxf(fmaxf(blo.x - me.x, me.x - bhi.x), 0.0f);
-            const float gy = fmaxf(fmaxf(blo.y - me.y, me.y - bhi.y), 0.0f);
-            const float gz = fmaxf(fmaxf(blo.z - me.z, me.z - bhi.z), 0.0f);
-            const float xx = gx * gx;
-            const float yy = gy * gy;
-            const float zz = gz * gz;
-            const float sxy = xx + yy;
-            M |= (act && sxy + zz <= bb) ? (1u << c) : 0u;
+            const float lo2 = point_low2_m<PER>(me.x, me.y, me.z, blo.x, blo.y, blo.z, bhi.x, bhi.y,
+                                                bhi.z, L);
+            M |= (act && lo2 <= bb) ? (1u << c) : 0u;
         }
         uint64_t lk[FTILE / 64] = {};
         const int nit = uni(wave_max_i(__popc(M)));
@@ -323,8 +319,8 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_fof(
             unsigned m8 = 0;
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
-                const float4 s = tile[tslot(c * 8 + u)];
-                const float dd = dist2_pts(me.x, me.y, me.z, s.x, s.y, s.z);
+                const float4 s = tile[fslot(c * 8 + u)];
+                const float dd = dist2_m<PER>(me.x, me.y, me.z, s.x, s.y, s.z, L, Lh);
                 m8 |= (u < real && cfirst + u > my && dd <= bb) ? (1u << u) : 0u;
             }
 #pragma unroll
@@ -459,6 +455,9 @@ jz_status run_fof(jz_tree *t, const float *b2_set_host, int32_t *label, hipStrea
 
     const bool sets = t->nsets > 1;
     const float b2 = b2_set_host[0];
+    // periodic cube of side L (L = 0: open)
+    const float L = t->opts.period;
+    const bool per = L > 0.0f;
     DBuf d_ctr, d_uf, d_min, d_b2set;
     // counters: one leaf statistic (evaluations)
     const size_t nctr = ctr_words(1);
@@ -502,23 +501,22 @@ jz_status run_fof(jz_tree *t, const float *b2_set_host, int32_t *label, hipStrea
             const int *whole_par = top ? nullptr : whole[p + 1].as<int>();
             const int64_t n_par = top ? t->S : t->L[p + 1];
             const float *bn = sets ? b2n[p].as<float>() : nullptr;
-            k_fof_p2n<<<blocks_for(n_par, WPB), 64 * WPB, 0, s>>>(par_spl, t->nodes[p].as<Node>(),
-                                                           (int)n_par, whole_par,
-                                                           whole[p].as<int>(), d_uf.as<int>(), b2,
-                                                           bn);
-            k_fof_step<<<blocks_for(n_par, WPB), 64 * WPB, 0, s>>>(
+            (per ? k_fof_p2n<true> : k_fof_p2n<false>)<<<blocks_for(n_par, WPB), 64 * WPB, 0, s>>>(
+                par_spl, t->nodes[p].as<Node>(), (int)n_par, whole_par, whole[p].as<int>(),
+                d_uf.as<int>(), b2, bn, L);
+            (per ? k_fof_step<true> : k_fof_step<false>)<<<blocks_for(n_par, WPB), 64 * WPB, 0, s>>>(
                 seg_in, list_in, par_spl, t->nodes[p].as<Node>(), (int)n_par, b2, bn,
                 whole[p].as<int>(), d_uf.as<int>(), segs[p].as<int2>(), lists[p].as<int2>(),
-                ctr + (size_t)p * LIST_ARENAS, cap[p] / LIST_ARENAS, ctr + CTR_FLAG);
+                ctr + (size_t)p * LIST_ARENAS, cap[p] / LIST_ARENAS, ctr + CTR_FLAG, L);
         }
         k_fof_l2p<<<blocks_for(t->L[0], WPB), 64 * WPB, 0, s>>>(t->nodes[0].as<Node>(), (int)t->L[0],
                                                          whole[0].as<int>(), d_uf.as<int>());
         JZ_HIP(hipGetLastError());
         if (ev.on) JZ_HIP(hipEventRecord(ev[1], s));
-        k_leaf_fof<<<blocks_for(t->L[0], WPB), 64 * WPB, 0, s>>>(
+        (per ? k_leaf_fof<true> : k_leaf_fof<false>)<<<blocks_for(t->L[0], WPB), 64 * WPB, 0, s>>>(
             segs[0].as<int2>(), lists[0].as<int2>(), t->nodes[0].as<Node>(), t->pts4.as<float4>(),
             (int)t->L[0], b2, sets ? b2n[0].as<float>() : nullptr, whole[0].as<int>(),
-            d_uf.as<int>(), ctr + CTR_STATS, ctr + CTR_FLAG);
+            d_uf.as<int>(), ctr + CTR_STATS, ctr + CTR_FLAG, L);
         if (ev.on) JZ_HIP(hipEventRecord(ev[2], s));
         k_flatten_min<<<blocks_for(n, 256), 256, 0, s>>>(d_uf.as<int>(), t->pts4.as<float4>(), n,
                                                           d_min.as<int>());

@@ -57,12 +57,104 @@ __device__ __forceinline__ float box_up2(const Node &a, const Node &b) {
     return s + zz;
 }
 
-// LDS slot of position j of a staged point tile (float4 per point): inside
-// each chunk of 8 positions the slots are permuted by the chunk's low 3 bits,
-// so that lanes reading the same position of different chunks at once spread
-// over the LDS banks (unpermuted, every chunk starts at a multiple of 128
-// bytes and all of them meet in one bank group).
-__device__ __forceinline__ int tslot(int j) { return j ^ ((j >> 3) & 7); }
+// ---------------------------------------------------------------------------
+// Periodic cube [0, L)^3 (build option `period`): the minimum-image
+// difference moves a coordinate difference by one period when it lies beyond
+// half of it (h = fl(L / 2)), and dist2 is the fixed expression of the
+// wrapped differences. PER = false is the open box above.
+
+template <bool PER>
+__device__ __forceinline__ float wrap_diff(float d, float L, float h) {
+    if constexpr (PER) {
+        d = d > h ? d - L : d;
+        d = d < -h ? d + L : d;
+    }
+    return d;
+}
+
+template <bool PER>
+__device__ __forceinline__ float dist2_m(float ax, float ay, float az, float bx, float by,
+                                         float bz, float L, float h) {
+    float dx = wrap_diff<PER>(ax - bx, L, h);
+    float dy = wrap_diff<PER>(ay - by, L, h);
+    float dz = wrap_diff<PER>(az - bz, L, h);
+    float xx = dx * dx;
+    float yy = dy * dy;
+    float zz = dz * dz;
+    float s = xx + yy;
+    return s + zz;
+}
+
+// Periodic bounds are not exact like the open ones: a wrapped difference
+// fl(fl(x - y) -+ L) may be off from the exact minimum-image difference by a
+// few units in the last place of L. Per axis the gap is lowered (the extent
+// raised) by 2^-21 L, and the sums get a relative margin of 2^-20, so the
+// bounds still bracket every computed member distance.
+__device__ __forceinline__ float per_gap(float dmin, float dmax, float L) {
+    // smallest |d + mL| over d in [dmin, dmax], m in {-1, 0, 1}
+    const float g0 = fmaxf(fmaxf(dmin, -dmax), 0.0f);
+    const float g1 = fmaxf(fmaxf(dmin - L, L - dmax), 0.0f);
+    const float g2 = fmaxf(fmaxf(dmin + L, -(dmax + L)), 0.0f);
+    return fminf(g0, fminf(g1, g2));
+}
+__device__ __forceinline__ float per_low_sum(float gx, float gy, float gz, float L) {
+    const float eps = L * 0x1p-21f;
+    gx = fmaxf(gx - eps, 0.0f);
+    gy = fmaxf(gy - eps, 0.0f);
+    gz = fmaxf(gz - eps, 0.0f);
+    const float xx = gx * gx, yy = gy * gy, zz = gz * gz;
+    const float s = xx + yy;
+    return (s + zz) * (1.0f - 0x1p-20f);
+}
+__device__ __forceinline__ float per_up_sum(float ux, float uy, float uz, float L) {
+    const float eps = L * 0x1p-21f, h = 0.5f * L;
+    ux = fminf(ux, h) + eps;
+    uy = fminf(uy, h) + eps;
+    uz = fminf(uz, h) + eps;
+    const float xx = ux * ux, yy = uy * uy, zz = uz * uz;
+    const float s = xx + yy;
+    return (s + zz) * (1.0f + 0x1p-20f);
+}
+
+// node-node bounds in the chosen metric
+template <bool PER>
+__device__ __forceinline__ float box_low2_m(const Node &a, const Node &b, float L) {
+    if constexpr (!PER) {
+        return box_low2(a, b);
+    } else {
+        return per_low_sum(per_gap(a.lo[0] - b.hi[0], a.hi[0] - b.lo[0], L),
+                           per_gap(a.lo[1] - b.hi[1], a.hi[1] - b.lo[1], L),
+                           per_gap(a.lo[2] - b.hi[2], a.hi[2] - b.lo[2], L), L);
+    }
+}
+template <bool PER>
+__device__ __forceinline__ float box_up2_m(const Node &a, const Node &b, float L) {
+    if constexpr (!PER) {
+        return box_up2(a, b);
+    } else {
+        return per_up_sum(fmaxf(a.hi[0] - b.lo[0], b.hi[0] - a.lo[0]),
+                          fmaxf(a.hi[1] - b.lo[1], b.hi[1] - a.lo[1]),
+                          fmaxf(a.hi[2] - b.lo[2], b.hi[2] - a.lo[2]), L);
+    }
+}
+// point-box lower bound in the chosen metric (box given by its corners)
+template <bool PER>
+__device__ __forceinline__ float point_low2_m(float qx, float qy, float qz, float lx, float ly,
+                                              float lz, float hx, float hy, float hz, float L) {
+    if constexpr (!PER) {
+        const float gx = fmaxf(fmaxf(lx - qx, qx - hx), 0.0f);
+        const float gy = fmaxf(fmaxf(ly - qy, qy - hy), 0.0f);
+        const float gz = fmaxf(fmaxf(lz - qz, qz - hz), 0.0f);
+        const float xx = gx * gx;
+        const float yy = gy * gy;
+        const float zz = gz * gz;
+        const float s = xx + yy;
+        return s + zz;
+    } else {
+        return per_low_sum(per_gap(qx - hx, qx - lx, L), per_gap(qy - hy, qy - ly, L),
+                           per_gap(qz - hz, qz - lz, L), L);
+    }
+}
 
 // ---------------------------------------------------------------------------
 // wave64 primitives

@@ -367,13 +367,14 @@ __global__ __launch_bounds__(64) void k_walk_items(const int *__restrict__ par_s
 //   pass 2  count pairs with d_low^2 <= R
 //   pass 3  insert them (with r_low = d_low^2) at offsets reserved with one
 //           atomic per wave; a child's entries are contiguous.
+template <bool PER>
 __global__ __launch_bounds__(64 * WPB) void k_knn_step(
     const int2 *__restrict__ items, const unsigned long long *__restrict__ n_items, int cb,
     const int2 *__restrict__ seg_in, int2 *__restrict__ list_in,
     const int *__restrict__ par_spl, const Node *__restrict__ nodes, int k,
     int2 *__restrict__ seg_out, int2 *__restrict__ list_out,
     unsigned long long *__restrict__ ctr, long long cap, unsigned long long *overflow,
-    int sort_cap, int presorted, const int *__restrict__ scnt) {
+    int sort_cap, int presorted, const int *__restrict__ scnt, float Lp) {
     // one block per wave: the staged list (LCAP entries), then the staged
     // source children (FCAP records and their indices); before the walk the
     // whole block is the scratch in which a longer list is sorted
@@ -422,7 +423,7 @@ __global__ __launch_bounds__(64 * WPB) void k_knn_step(
             [&](int nF) {
                 for (int f = sl; f < nF; f += G) {
                     const Node o = F[f];
-                    const float r = box_up2(me, o);
+                    const float r = box_up2_m<PER>(me, o, Lp);
                     if (act && r < R && o.count > 0) {
                         heap_insert<NR_HEAP>(hr, hc, r, o.count);
                         R = fminf(R, radius_of_count<NR_HEAP>(hr, hc, k));
@@ -467,7 +468,7 @@ __global__ __launch_bounds__(64 * WPB) void k_knn_step(
             [&](int nF) {
                 for (int f = sl; f < nF; f += G) {
                     const Node o = F[f];
-                    cnt += (act && o.count > 0 && box_low2(me, o) <= R) ? 1 : 0;
+                    cnt += (act && o.count > 0 && box_low2_m<PER>(me, o, Lp) <= R) ? 1 : 0;
                 }
             });
         // reserve: lanes are child-major, so a wave scan gives contiguous segments
@@ -497,7 +498,7 @@ __global__ __launch_bounds__(64 * WPB) void k_knn_step(
             [&](int nF) {
                 for (int f = sl; f < nF; f += G) {
                     const Node o = F[f];
-                    const float lo = box_low2(me, o);
+                    const float lo = box_low2_m<PER>(me, o, Lp);
                     if (act && o.count > 0 && lo <= R) {
                         list_out[wp] = make_int2(FI[f], __float_as_int(lo));
                         ++wp;
@@ -561,22 +562,17 @@ __device__ __forceinline__ void topk_insert(TopK<K> &b, double key) {
     }
 }
 
-// lower bound of dist2 from a point to any point of a box (monotone, exact)
-__device__ __forceinline__ float point_box_low2(const float4 &q, const Node &b) {
-    const float gx = fmaxf(fmaxf(b.lo[0] - q.x, q.x - b.hi[0]), 0.0f);
-    const float gy = fmaxf(fmaxf(b.lo[1] - q.y, q.y - b.hi[1]), 0.0f);
-    const float gz = fmaxf(fmaxf(b.lo[2] - q.z, q.z - b.hi[2]), 0.0f);
-    const float xx = gx * gx;
-    const float yy = gy * gy;
-    const float zz = gz * gz;
-    const float s = xx + yy;
-    return s + zz;
-}
-
 constexpr int SB = 16;        // source leaves examined per batch
 constexpr int TILE_PTS = 256; // source points staged per batch (positions fit a byte)
 constexpr int CQ = 32;        // queued candidate positions per lane
 constexpr int CH = 8;         // tile positions a lane scans between queue checks
+
+// LDS slot of tile position j: inside each chunk of 8 positions the slots are
+// permuted by the chunk's low 3 bits, so that lanes reading the same position
+// of different chunks at once spread over the LDS banks (unpermuted, every
+// chunk starts at a multiple of 128 bytes and all of them meet in one bank
+// group).
+__device__ __forceinline__ int tslot(int j) { return j ^ ((j >> 3) & 7); }
 
 
 // Keep the K smallest of two ascending key lists a and b in a (ascending).
@@ -696,14 +692,16 @@ __device__ __forceinline__ void merge_chunk(TopK<K> &a, const double (&ch)[C]) {
 // back from column col0 - 1 of the output row), so that equal distances
 // continue by index. A pass writes columns [col0, col0 + kw) of rows of
 // out_stride entries.
-template <int K, bool LO>
+template <int K, bool LO, bool PER>
 __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
     const int2 *__restrict__ seg, int2 *__restrict__ list, const Node *__restrict__ leaves,
     const float4 *__restrict__ pts, int n_leaves, const int *__restrict__ leaf_base,
     int32_t *__restrict__ out_idx, float *__restrict__ out_d2,
     unsigned long long *__restrict__ stats, const unsigned long long *__restrict__ overflow,
     int sort_cap, int presorted, int out_stride, int col0, int kw,
-    const int *__restrict__ scnt0, int src_hi, int qry_lo) {
+    const int *__restrict__ scnt0, int src_hi, int qry_lo, float Lp) {
+    // Lp: period of the cube (PER), Lh its half
+    const float Lh = 0.5f * Lp;
     // one block per wave: the staged list (LCAP entries), the point tile,
     // the (lo, hi) box of every 8 tile positions and the candidate queues;
     // before the walk the whole block is the scratch in which a longer list
@@ -797,7 +795,7 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
                 const int slot = min(c + u, CQ - 1);
                 const int qv = q0[64 * slot];
                 const float4 s = tile[c + u < qn ? qv : 0];
-                const float dd = dist2_pts(me.x, me.y, me.z, s.x, s.y, s.z);
+                const float dd = dist2_m<PER>(me.x, me.y, me.z, s.x, s.y, s.z, Lp, Lh);
                 const double kk = key_of(dd, __float_as_int(s.w));
                 ch[u] = (c + u < qn && (!LO || kk > lo)) ? kk : pad;
             }
@@ -846,7 +844,9 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
         wave_lds_sync();
         unsigned needbits = 0;
         for (int qq = 0; qq < nb_n; ++qq)
-            if (act && point_box_low2(me, nb[qq]) <= kth) needbits |= 1u << qq;
+            if (act && point_low2_m<PER>(me.x, me.y, me.z, nb[qq].lo[0], nb[qq].lo[1], nb[qq].lo[2],
+                                         nb[qq].hi[0], nb[qq].hi[1], nb[qq].hi[2], Lp) <= kth)
+                needbits |= 1u << qq;
         const unsigned any = uni(wave_or(needbits));
         // take needed sources in order while their points fit the tile; each
         // occupies a multiple of 8 positions, one box per 8 (every lane
@@ -931,7 +931,7 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
                         for (int u = 0; u < C; ++u) {
                             if (j0 + u * SS < f1) {
                                 const float4 p = tile[tslot(j0 + u * SS + h)];
-                                const float dd = dist2_pts(me.x, me.y, me.z, p.x, p.y, p.z);
+                                const float dd = dist2_m<PER>(me.x, me.y, me.z, p.x, p.y, p.z, Lp, Lh);
                                 const double kk = key_of(dd, __float_as_int(p.w));
                                 ch[u] = (!LO || kk > lo) ? kk : pad;
                             } else {
@@ -961,14 +961,9 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
             for (int c = 0; c < nch; ++c) {
                 const float4 *bx = cbox + c * 2;
                 const float4 blo = bx[0], bhi = bx[1];
-                const float gx = fmaxf(fmaxf(blo.x - me.x, me.x - bhi.x), 0.0f);
-                const float gy = fmaxf(fmaxf(blo.y - me.y, me.y - bhi.y), 0.0f);
-                const float gz = fmaxf(fmaxf(blo.z - me.z, me.z - bhi.z), 0.0f);
-                const float xx = gx * gx;
-                const float yy = gy * gy;
-                const float zz = gz * gz;
-                const float sxy = xx + yy;
-                M |= (act && sxy + zz <= kth) ? (1u << c) : 0u;
+                const float lo2 = point_low2_m<PER>(me.x, me.y, me.z, blo.x, blo.y, blo.z, bhi.x,
+                                                    bhi.y, bhi.z, Lp);
+                M |= (act && lo2 <= kth) ? (1u << c) : 0u;
             }
             const int nit = uni(wave_max_i(__popc(M)));
             for (int it = 0; it < nit; ++it) {
@@ -980,7 +975,7 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
                 for (int u = 0; u < 8 / SS; ++u) {
                     const int j = tslot(c * 8 + u * SS + h);
                     const float4 p = tile[j];
-                    const float dd = dist2_pts(me.x, me.y, me.z, p.x, p.y, p.z);
+                    const float dd = dist2_m<PER>(me.x, me.y, me.z, p.x, p.y, p.z, Lp, Lh);
                     // written always, kept only if accepted (at most CH
                     // positions per pop from qn <= CQ - CH: the slot exists)
                     *qp = (uint8_t)j;
@@ -1043,25 +1038,38 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
 
 typedef void (*leaf_fn)(const int2 *, int2 *, const Node *, const float4 *, int, const int *,
                         int32_t *, float *, unsigned long long *, const unsigned long long *, int,
-                        int, int, int, int, const int *, int, int);
+                        int, int, int, int, const int *, int, int, float);
 
-template <int K>
+template <int K, bool LO, bool PER>
 leaf_fn leaf_ptr() {
-    return k_leaf_knn<K, false>;
+    return k_leaf_knn<K, LO, PER>;
 }
 
-// the leaf kernel of a first pass with K = k (k <= 32); later passes of a
-// k > 32 search use k_leaf_knn<32, true>
-leaf_fn leaf_kernel(int k) {
-    static const leaf_fn table[33] = {
-        nullptr,       leaf_ptr<1>(),  leaf_ptr<2>(),  leaf_ptr<3>(),  leaf_ptr<4>(),
-        leaf_ptr<5>(), leaf_ptr<6>(),  leaf_ptr<7>(),  leaf_ptr<8>(),  leaf_ptr<9>(),
-        leaf_ptr<10>(), leaf_ptr<11>(), leaf_ptr<12>(), leaf_ptr<13>(), leaf_ptr<14>(),
-        leaf_ptr<15>(), leaf_ptr<16>(), leaf_ptr<17>(), leaf_ptr<18>(), leaf_ptr<19>(),
-        leaf_ptr<20>(), leaf_ptr<21>(), leaf_ptr<22>(), leaf_ptr<23>(), leaf_ptr<24>(),
-        leaf_ptr<25>(), leaf_ptr<26>(), leaf_ptr<27>(), leaf_ptr<28>(), leaf_ptr<29>(),
-        leaf_ptr<30>(), leaf_ptr<31>(), leaf_ptr<32>()};
-    return table[k];
+template <bool PER>
+leaf_fn leaf_kernel_m(int k, bool lo) {
+    static const leaf_fn table[34] = {
+        nullptr,
+        leaf_ptr<1, false, PER>(),  leaf_ptr<2, false, PER>(),  leaf_ptr<3, false, PER>(),
+        leaf_ptr<4, false, PER>(),  leaf_ptr<5, false, PER>(),  leaf_ptr<6, false, PER>(),
+        leaf_ptr<7, false, PER>(),  leaf_ptr<8, false, PER>(),  leaf_ptr<9, false, PER>(),
+        leaf_ptr<10, false, PER>(), leaf_ptr<11, false, PER>(), leaf_ptr<12, false, PER>(),
+        leaf_ptr<13, false, PER>(), leaf_ptr<14, false, PER>(), leaf_ptr<15, false, PER>(),
+        leaf_ptr<16, false, PER>(), leaf_ptr<17, false, PER>(), leaf_ptr<18, false, PER>(),
+        leaf_ptr<19, false, PER>(), leaf_ptr<20, false, PER>(), leaf_ptr<21, false, PER>(),
+        leaf_ptr<22, false, PER>(), leaf_ptr<23, false, PER>(), leaf_ptr<24, false, PER>(),
+        leaf_ptr<25, false, PER>(), leaf_ptr<26, false, PER>(), leaf_ptr<27, false, PER>(),
+        leaf_ptr<28, false, PER>(), leaf_ptr<29, false, PER>(), leaf_ptr<30, false, PER>(),
+        leaf_ptr<31, false, PER>(), leaf_ptr<32, false, PER>(), leaf_ptr<32, true, PER>()};
+    return table[lo ? 33 : k];
+}
+
+// The leaf kernel of one pass: K = k for k <= 32 (one pass); for k > 32 the
+// first pass has K = 32 and the later ones continue after the last key of the
+// pass before (LO).
+leaf_fn leaf_kernel(int k, int col, bool per) {
+    const int kk = k <= 32 ? k : 32;
+    const bool lo = col > 0;
+    return per ? leaf_kernel_m<true>(kk, lo) : leaf_kernel_m<false>(kk, lo);
 }
 
 }  // namespace
@@ -1087,6 +1095,9 @@ jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s,
     const int P = t->P;
     // a joint tree of source and query points: rows are the query points
     const bool joint = t->n_src >= 0;
+    // periodic cube (period 0: open)
+    const float period = t->opts.period;
+    const bool per = period > 0.0f;
     for (int p = 0; p <= JZ_MAX_PLANES; ++p) t->st.list_entries[p] = 0;
     t->st.leaf_pairs = t->st.leaf_pairs_visited = 0;
     t->st.evaluations = 0;
@@ -1175,12 +1186,13 @@ jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s,
             unsigned long long *n_items = ctr + c_items + p;
             k_walk_items<<<(unsigned)((n_par + 63) / 64), 64, 0, s>>>(
                 par_spl, (int)n_par, cb_of(p), d_items.as<int2>(), n_items);
-            k_knn_step<<<blocks_for(item_bound(p), WPB), 64 * WPB, 0, s>>>(
+            (per ? k_knn_step<true> : k_knn_step<false>)<<<blocks_for(item_bound(p), WPB),
+                                                              64 * WPB, 0, s>>>(
                 d_items.as<int2>(), n_items, cb_of(p), seg_in, list_in, par_spl,
                 t->nodes[p].as<Node>(), k, segs[p].as<int2>(), lists[p].as<int2>(),
                 ctr + (size_t)p * LIST_ARENAS, cap[p] / LIST_ARENAS, ctr + CTR_FLAG,
                 top ? LCAP : walk_cap, top ? 0 : sort_max,
-                joint ? t->src_cnt[p].as<int>() : nullptr);
+                joint ? t->src_cnt[p].as<int>() : nullptr, period);
         }
         presort(lists[0].as<int2>(), segs[0].as<int2>(), t->L[0], leaf_cap,
                 ctr + c_long + 2 * JZ_MAX_PLANES);
@@ -1189,14 +1201,13 @@ jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s,
         // k <= 32: one pass; larger k: passes of 32 neighbours, each after
         // the last key of the one before
         for (int col = 0; col < k; col += 32) {
-            const leaf_fn fn = k <= 32 ? leaf_kernel(k)
-                                       : (col == 0 ? leaf_kernel(32) : k_leaf_knn<32, true>);
+            const leaf_fn fn = leaf_kernel(k, col, per);
             fn<<<blocks_for(t->L[0], WPB), 64 * WPB, 0, s>>>(
                 segs[0].as<int2>(), lists[0].as<int2>(), t->nodes[0].as<Node>(),
                 t->pts4.as<float4>(), (int)t->L[0], t->nsets > 1 ? t->leaf_base.as<int>() : nullptr,
                 idx, dist2, ctr + CTR_STATS, ctr + CTR_FLAG, leaf_cap, sort_max, k, col,
                 std::min(32, k - col), joint ? t->src_cnt[0].as<int>() : nullptr,
-                joint ? (int)t->n_src : INT_MAX, joint ? (int)t->n_src : 0);
+                joint ? (int)t->n_src : INT_MAX, joint ? (int)t->n_src : 0, period);
             JZ_HIP(hipGetLastError());
         }
         if (ev.on) JZ_HIP(hipEventRecord(ev[2], s));

@@ -356,3 +356,24 @@ def test_full_size_clustered(jz, fp64_log):
                     "binary64 %d, partition differs: %s (%d points relabelled)" % (
                         rep["pairs_f32_only"], rep["pairs_f64_only"], rep["partition_differs"],
                         rep["points_relabelled"]))
+
+
+def test_regularization_same_results_smaller_nodes(jz):
+    """A tight Gaussian with a few points far from the bulk (the paper's case
+    for regularization): with reg_fmax = 50 the far points no longer share
+    huge nodes (more leaves), and every result is still exact."""
+    rng = np.random.default_rng(61)
+    bulk = (0.5 + 0.01 * rng.standard_normal((30000, 3))).astype(np.float32)
+    far = rng.random((40, 3)).astype(np.float32)
+    p = np.concatenate([bulk, far])[rng.permutation(30040)]
+    wi, wd = oracle.knn_bf(p, 16)
+    b = inputs.linking_length(30040, 0.3) * 0.05
+    wl = oracle.fof_bf(p, b)
+    leaves = []
+    for fmax in (0.0, 50.0):
+        gi, gd, st = gpu_knn(jz, p, 16, reg_fmax=fmax)
+        assert_knn_equal(gi, gd, wi, wd, "reg_fmax=%g" % fmax)
+        lab, _ = gpu_fof(jz, p, b, reg_fmax=fmax)
+        assert np.array_equal(lab, wl), fmax
+        leaves.append(st["nodes"][0])
+    assert leaves[1] > leaves[0], leaves
