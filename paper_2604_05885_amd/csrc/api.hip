@@ -230,7 +230,7 @@ jz_status check_opts(const jz_build_opts &o) {
     if (o.coarsen < 2 || o.coarsen > 64) return jz_fail(JZ_E_INVALID, "coarsen must be in [2, 64]");
     if (o.n_target < 1) return jz_fail(JZ_E_INVALID, "n_target must be >= 1");
     if (o.ngr < 1 || o.ngr > 64) return jz_fail(JZ_E_INVALID, "ngr must be in [1, 64]");
-    if (o.key_bits < 1 || o.key_bits > 21) return jz_fail(JZ_E_INVALID, "key_bits must be in [1, 21]");
+    if (o.key_bits < 0 || o.key_bits > 21) return jz_fail(JZ_E_INVALID, "key_bits must be in [0, 21]");
     if (!(o.list_per_node >= 1.0f) || !std::isfinite(o.list_per_node))
         return jz_fail(JZ_E_INVALID, "list_per_node must be finite and >= 1");
     if (o.sort_max < 256 || o.sort_max > 8192)
@@ -309,7 +309,7 @@ void jz_default_opts(jz_build_opts *o) {
     o->coarsen = 8;
     o->n_target = 1000;
     o->ngr = 32;
-    o->key_bits = 21;
+    o->key_bits = 0;
     o->list_per_node = 96.0f;
     o->auto_regrow = 1;
     o->keep_keys = 0;

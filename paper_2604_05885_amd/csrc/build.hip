@@ -787,7 +787,14 @@ jz_status build_tree(jz_tree *t, const float *points, hipStream_t s) {
     if (n == 0) return JZ_OK;
 
     const int has_sets = t->nsets > 1;
+    // automatic key bits: 8 more per dimension than an even split of n
+    // points needs (cells well below the mean spacing), at most 21
     int bits = o.key_bits;
+    if (bits == 0) {
+        int lg = 0;
+        while (lg < 62 && ((int64_t)1 << lg) < n) ++lg;
+        bits = std::min(21, std::max(10, (lg + 2) / 3 + 8));
+    }
     const int max_bits = (63 - t->set_bits) / 3;
     if (bits > max_bits) bits = max_bits;
     const int bits3 = 3 * bits;

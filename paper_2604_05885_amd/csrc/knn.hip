@@ -374,7 +374,8 @@ __global__ __launch_bounds__(64 * WPB) void k_knn_step(
     const int *__restrict__ par_spl, const Node *__restrict__ nodes, int k,
     int2 *__restrict__ seg_out, int2 *__restrict__ list_out,
     unsigned long long *__restrict__ ctr, long long cap, unsigned long long *overflow,
-    int sort_cap, int presorted, const int *__restrict__ scnt, float Lp) {
+    int sort_cap, int presorted, const int *__restrict__ scnt, float Lp,
+    float *__restrict__ rout) {
     // one block per wave: the staged list (LCAP entries), then the staged
     // source children (FCAP records and their indices); before the walk the
     // whole block is the scratch in which a longer list is sorted
@@ -460,6 +461,9 @@ __global__ __launch_bounds__(64 * WPB) void k_knn_step(
             R = fminf(best, R);
             wave_lds_sync();
         }
+        // the leaf level keeps each child's radius for the leaf stage: k
+        // points lie within R of every point of the child
+        if (rout && act && sl == 0) rout[c] = R;
         const float Rw = uni(wave_max_f(act ? R : -INFINITY));
         // pass 2: count
         int cnt = 0;
@@ -699,7 +703,8 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
     int32_t *__restrict__ out_idx, float *__restrict__ out_d2,
     unsigned long long *__restrict__ stats, const unsigned long long *__restrict__ overflow,
     int sort_cap, int presorted, int out_stride, int col0, int kw,
-    const int *__restrict__ scnt0, int src_hi, int qry_lo, float Lp) {
+    const int *__restrict__ scnt0, int src_hi, int qry_lo, float Lp,
+    const float *__restrict__ rleaf) {
     // Lp: period of the cube (PER), Lh its half
     const float Lh = 0.5f * Lp;
     // one block per wave: the staged list (LCAP entries), the point tile,
@@ -771,11 +776,15 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
     const uint8_t *const qlim = q0 + 64 * (CQ - CH);
 
     // the group's k-th distance: an upper bound of the query's final k-th
+    // the walk's radius of this leaf: the k-th distance of each of its
+    // points is at most R (k = all passes' neighbours, so it bounds every
+    // pass), so nothing farther is ever needed
+    const float Rleaf = uni(rleaf[A]);
     auto group_kth = [&]() {
         float v = key_dist(best.get(K - 1));
         if (lgS >= 1) v = fminf(v, swap32_f(v));
         if (lgS >= 2) v = fminf(v, swap16_f(v));
-        return v;
+        return fminf(v, Rleaf);
     };
     // insert the queued candidates of every lane into its top-k: 8 at a time,
     // sorted in registers and merged (the busiest lane sets the trip count,
@@ -1038,7 +1047,7 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
 
 typedef void (*leaf_fn)(const int2 *, int2 *, const Node *, const float4 *, int, const int *,
                         int32_t *, float *, unsigned long long *, const unsigned long long *, int,
-                        int, int, int, int, const int *, int, int, float);
+                        int, int, int, int, const int *, int, int, float, const float *);
 
 template <int K, bool LO, bool PER>
 leaf_fn leaf_ptr() {
@@ -1145,8 +1154,9 @@ jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s,
     for (int p = 0; p < P; ++p) max_items = std::max(max_items, item_bound(p));
     DBuf d_items;
     JZ_TRY(d_items.get(ac, (size_t)max_items * sizeof(int2), s));
-    DBuf d_ids;
+    DBuf d_ids, d_rleaf;
     JZ_TRY(d_ids.get(ac, 2 * (size_t)t->L[0] * sizeof(int), s));
+    JZ_TRY(d_rleaf.get(ac, (size_t)t->L[0] * sizeof(float), s));
     auto presort = [&](int2 *list, const int2 *seg, int64_t n, int min_len,
                        unsigned long long *count) {
         if (sort_max <= min_len) return;
@@ -1192,7 +1202,8 @@ jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s,
                 t->nodes[p].as<Node>(), k, segs[p].as<int2>(), lists[p].as<int2>(),
                 ctr + (size_t)p * LIST_ARENAS, cap[p] / LIST_ARENAS, ctr + CTR_FLAG,
                 top ? LCAP : walk_cap, top ? 0 : sort_max,
-                joint ? t->src_cnt[p].as<int>() : nullptr, period);
+                joint ? t->src_cnt[p].as<int>() : nullptr, period,
+                p == 0 ? d_rleaf.as<float>() : nullptr);
         }
         presort(lists[0].as<int2>(), segs[0].as<int2>(), t->L[0], leaf_cap,
                 ctr + c_long + 2 * JZ_MAX_PLANES);
@@ -1207,7 +1218,8 @@ jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s,
                 t->pts4.as<float4>(), (int)t->L[0], t->nsets > 1 ? t->leaf_base.as<int>() : nullptr,
                 idx, dist2, ctr + CTR_STATS, ctr + CTR_FLAG, leaf_cap, sort_max, k, col,
                 std::min(32, k - col), joint ? t->src_cnt[0].as<int>() : nullptr,
-                joint ? (int)t->n_src : INT_MAX, joint ? (int)t->n_src : 0, period);
+                joint ? (int)t->n_src : INT_MAX, joint ? (int)t->n_src : 0, period,
+                d_rleaf.as<float>());
             JZ_HIP(hipGetLastError());
         }
         if (ev.on) JZ_HIP(hipEventRecord(ev[2], s));

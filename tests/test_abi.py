@@ -19,7 +19,7 @@ def test_library_exports_every_header_symbol():
 
 def test_default_opts():
     o = api.default_opts()
-    assert (o.leaf_max, o.coarsen, o.n_target, o.ngr, o.key_bits) == (64, 8, 1000, 32, 21)
+    assert (o.leaf_max, o.coarsen, o.n_target, o.ngr, o.key_bits) == (64, 8, 1000, 32, 0)
     assert o.sort_max == 8192
     assert o.auto_regrow == 1 and o.keep_keys == 0 and o.list_per_node == 96.0
 

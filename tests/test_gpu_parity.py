@@ -286,7 +286,7 @@ def test_tree_against_plane_reference(jz):
     """Sorted order, Morton keys and every plane's splits against the
     oracle's plane construction (oracle.planes) on the same keys."""
     p = inputs.clustered(30000, 12, 41)
-    opts = jz.default_opts(keep_keys=1, n_target=10)
+    opts = jz.default_opts(keep_keys=1, n_target=10, key_bits=21)
     with jz.jz_build(to_dev(p), opts) as t:
         st = t.stats()
         ex = t.export(order=True, keys=True)
