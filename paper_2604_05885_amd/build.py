@@ -29,11 +29,14 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-# knn.hip orders top-k keys as doubles with v_min_f64 / v_max_f64; no value
-# there is ever NaN, so NaN handling (and the IEEE-mode canonicalizations it
-# needs) is switched off for that file. Rounding and subnormal handling are
+# knn.hip orders top-k keys as doubles with v_min_f64 / v_max_f64, and both
+# leaf stages reduce boxes with min / max; no value in these files is ever
+# NaN (coordinates are finite, fillers sit at +-inf and never meet inf - inf),
+# so NaN handling (and the IEEE-mode canonicalizations it needs around every
+# min / max) is switched off for them. Rounding and subnormal handling are
 # unaffected.
-EXTRA = {"knn.hip": ["-fno-honor-nans", "-mno-amdgpu-ieee"]}
+EXTRA = {"knn.hip": ["-fno-honor-nans", "-mno-amdgpu-ieee"],
+         "fof.hip": ["-fno-honor-nans", "-mno-amdgpu-ieee"]}
 
 
 def _compile(src: str, verbose: bool) -> str:

@@ -377,3 +377,18 @@ def test_regularization_same_results_smaller_nodes(jz):
         assert np.array_equal(lab, wl), fmax
         leaves.append(st["nodes"][0])
     assert leaves[1] > leaves[0], leaves
+
+
+@pytest.mark.parametrize("key_bits", [1, 4, 10, 21])
+def test_key_width_never_changes_results(jz, key_bits):
+    """Coarse Morton keys make many points share a key (equal keys are cut
+    into aligned power-of-two runs of sorted positions); the automatic width
+    and explicit widths must all give the exact result."""
+    p = inputs.clustered(20000, 16, 71)
+    wi, wd = oracle.knn_bf(p, 16)
+    b = inputs.linking_length(20000, 0.2)
+    wl = oracle.fof_bf(p, b)
+    gi, gd, _ = gpu_knn(jz, p, 16, key_bits=key_bits)
+    assert_knn_equal(gi, gd, wi, wd, "key_bits=%d" % key_bits)
+    lab, _ = gpu_fof(jz, p, b, key_bits=key_bits)
+    assert np.array_equal(lab, wl), key_bits
