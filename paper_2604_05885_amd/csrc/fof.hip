@@ -359,16 +359,20 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_fof(
                 rootT[lane] = uf_find(uf, b0 + lane);
             }
             wave_lds_sync();
-            // 3: unite where the roots differ
+            // 3: unite where the roots differ. Groups only merge, so a point
+            // whose looked-up root is one this lane has just united with is
+            // connected already.
             if (lm) {
                 if (ra < 0) ra = uf_find(uf, my);
+                int last = -1;
                 while (lm) {
                     const int f = __ffsll((unsigned long long)lm) - 1;
                     lm &= lm - 1;
                     const int rj = wB ? rB : rootT[f];
-                    if (rj != ra) {
+                    if (rj != ra && rj != last) {
                         uf_union(uf, my, b0 + f);
                         ra = uf_find(uf, my);
+                        last = rj;
                     }
                 }
             }
