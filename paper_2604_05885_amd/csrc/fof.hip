@@ -332,7 +332,7 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_fof(
             if (!((any >> q) & 1u)) continue;
             const bool wB = (wholemask >> q) & 1u;
             const int f0 = uni(offs[q]), f1 = uni(offs[q + 1]);
-            const int b0 = uni(nb[q].start), cnt = uni(nb[q].count);
+            const int b0 = uni(nb[q].start);
             // this source's positions [f0, f1) of the tile link mask (f0 is a
             // multiple of 8 and a source spans at most 64 positions)
             const int h0 = f0 >> 6, sh = f0 & 63;
@@ -351,12 +351,15 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_fof(
                 if (lane == leader) uf_union(uf, my, b0 + __ffsll((unsigned long long)lm) - 1);
                 continue;
             }
-            // 2: roots of the source's points, looked up in parallel
+            // 2: roots of the source's points that some lane links to,
+            // looked up in parallel
             int rB = -1;
             if (wB) {
                 rB = uf_find(uf, b0);
-            } else if (lane < cnt) {
-                rootT[lane] = uf_find(uf, b0 + lane);
+            } else {
+                const uint64_t want = ((uint64_t)wave_or((unsigned)(lm >> 32)) << 32) |
+                                      wave_or((unsigned)lm);
+                if ((want >> lane) & 1ull) rootT[lane] = uf_find(uf, b0 + lane);
             }
             wave_lds_sync();
             // 3: unite where the roots differ. Groups only merge, so a point
