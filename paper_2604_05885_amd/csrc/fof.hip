@@ -231,7 +231,7 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_fof(
     unsigned evals = 0;
     for (int t = 0; t < len;) {
         const int nb_n = min(FSB, len - t);
-        const int rA = wA ? uni(uf_find(uf, astart)) : -1;
+        const int rA = wA ? uni(uf_find_c(uf, astart)) : -1;
         bool skip = false;
         int wB = 0;
         if (lane < nb_n) {
@@ -239,7 +239,7 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_fof(
             const Node b = leaves[B];
             nb[lane] = b;
             wB = whole[B];
-            skip = wA && wB && uf_find(uf, b.start) == rA;
+            skip = wA && wB && uf_find_c(uf, b.start) == rA;
         }
         const unsigned skipmask = (unsigned)__ballot(skip);
         const unsigned wholemask = (unsigned)__ballot(lane < nb_n && wB);
@@ -348,33 +348,33 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_fof(
             if (wA && wB) {
                 // both leaves are whole: a single link joins them
                 const int leader = __ffsll((unsigned long long)linking) - 1;
-                if (lane == leader) uf_union(uf, my, b0 + __ffsll((unsigned long long)lm) - 1);
+                if (lane == leader) uf_union_c(uf, my, b0 + __ffsll((unsigned long long)lm) - 1);
                 continue;
             }
             // 2: roots of the source's points that some lane links to,
             // looked up in parallel
             int rB = -1;
             if (wB) {
-                rB = uf_find(uf, b0);
+                rB = uf_find_c(uf, b0);
             } else {
                 const uint64_t want = ((uint64_t)wave_or((unsigned)(lm >> 32)) << 32) |
                                       wave_or((unsigned)lm);
-                if ((want >> lane) & 1ull) rootT[lane] = uf_find(uf, b0 + lane);
+                if ((want >> lane) & 1ull) rootT[lane] = uf_find_c(uf, b0 + lane);
             }
             wave_lds_sync();
             // 3: unite where the roots differ. Groups only merge, so a point
             // whose looked-up root is one this lane has just united with is
             // connected already.
             if (lm) {
-                if (ra < 0) ra = uf_find(uf, my);
+                if (ra < 0) ra = uf_find_c(uf, my);
                 int last = -1;
                 while (lm) {
                     const int f = __ffsll((unsigned long long)lm) - 1;
                     lm &= lm - 1;
                     const int rj = wB ? rB : rootT[f];
                     if (rj != ra && rj != last) {
-                        uf_union(uf, my, b0 + f);
-                        ra = uf_find(uf, my);
+                        uf_union_c(uf, my, b0 + f);
+                        ra = uf_find_c(uf, my);
                         last = rj;
                     }
                 }

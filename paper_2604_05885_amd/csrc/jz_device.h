@@ -374,6 +374,46 @@ __device__ __forceinline__ void uf_union(int *par, int a, int b) {
     }
 }
 
+// The same operations with parent pointers read through this CU's and this
+// XCD's caches (device-scope reads go past the per-XCD L2 to memory): a read
+// may return an older value, never a wrong one, because a parent only ever
+// moves to an ancestor. An older parent is still an ancestor, an older root
+// is still a member of the group, and equal roots, however old, mean one
+// group (groups only merge). Every write stays device-coherent: the
+// path-halving store puts an ancestor (found from possibly older reads) into
+// a node that is not a root, which only the halving itself ever rewrites, and
+// the compare-and-swap on a root fails on a stale guess and returns the
+// current parent, which is smaller, so union's retry loop ends (the larger of
+// its two ids strictly decreases).
+__device__ __forceinline__ int ld_cached(const int *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ int uf_find_c(int *par, int x) {
+    while (true) {
+        int p = ld_cached(par + x);
+        if (p == x) return x;
+        int gp = ld_cached(par + p);
+        if (gp == p) return p;
+        st_rel(par + x, gp);
+        x = gp;
+    }
+}
+__device__ __forceinline__ void uf_union_c(int *par, int a, int b) {
+    while (true) {
+        a = uf_find_c(par, a);
+        b = uf_find_c(par, b);
+        if (a == b) return;
+        if (a > b) {
+            int t = a;
+            a = b;
+            b = t;
+        }
+        int old = atomicCAS(par + b, b, a);
+        if (old == b) return;
+        b = old;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
 // L2). Remap so that each XCD works on runs of XCD_RUN consecutive
