@@ -81,11 +81,14 @@ __device__ __forceinline__ int fof_case(const Node &me, int c, const Node &o, in
                                         int *whole, int *uf, bool do_link, float &lo, float L) {
     lo = box_low2_m<PER>(me, o, L);
     if (lo > bb) return kDiscard;
-    if (ld_acq(whole + c) && ld_acq(whole + s) && uf_find(uf, me.start) == uf_find(uf, o.start))
+    // (flags only ever go from 0 to 1 and groups only merge: values read
+    // through the caches may be older, which only costs a redundant union)
+    if (ld_cached(whole + c) && ld_cached(whole + s) &&
+        uf_find_c(uf, me.start) == uf_find_c(uf, o.start))
         return kDiscard;
     if (box_up2_m<PER>(me, o, L) <= bb) {
         if (do_link) {
-            uf_union(uf, me.start, o.start);
+            uf_union_c(uf, me.start, o.start);
             st_rel(whole + c, 1);
             st_rel(whole + s, 1);
         }
@@ -401,11 +404,13 @@ __global__ __launch_bounds__(256) void k_flatten_min(int *__restrict__ uf,
     const int lane = lane_id();
     int root = -1 - lane, v = INT_MAX;  // invalid lanes: a root of their own
     if (valid) {
+        // (a parent read through the caches may be an older one: still an
+        // ancestor, so the walk still ends at the root)
         int x = (int)i;
-        int p = ld_acq(uf + x);
+        int p = ld_cached(uf + x);
         while (p != x) {
             x = p;
-            p = ld_acq(uf + x);
+            p = ld_cached(uf + x);
         }
         root = x;
         uf[i] = x;
