@@ -251,9 +251,16 @@ constexpr int FCAP = 128;  // source children staged per batch
 // children of consecutive sources are copied into one LDS buffer (their node
 // records in F, their indices in FI) until FCAP children; a source with more
 // children than FCAP is split over several batches. Sources whose r_low
-// exceeds rw() (re-evaluated per batch) end the walk. fn(nF) then processes
-// the nF staged children. The list entries of the next batch and their
-// children ranges are loaded while fn runs on the current one.
+// exceeds rw() end the walk. fn(nF, fi) then processes the nF staged children
+// (fi: their indices).
+// The walk is pipelined one batch deep: the next batch is chosen, its indices
+// written to the other half of FI and its node records loaded into registers
+// before fn runs on the current one, and copied into F after it, so that the
+// record loads overlap fn instead of stalling every batch. The next batch is
+// chosen with rw() as it was before fn; where rw() shrinks during fn (the
+// FindRmax pass) that may take sources a later check would have dropped, which
+// only adds candidates to an upper bound. The list entries (and children
+// ranges) of the batch after that are loaded meanwhile too.
 // With separate query and source points (scnt != nullptr), a staged record's
 // count is replaced by its number of source points.
 template <class RW, class FN>
@@ -263,6 +270,7 @@ __device__ __forceinline__ void for_source_batches(bool staged, const uint64_t *
                                                    const Node *__restrict__ nodes,
                                                    const int *__restrict__ scnt, Node *F, int *FI,
                                                    RW &&rw, FN &&fn) {
+    static_assert(FCAP == 128, "two node records per lane");
     const int lane = lane_id();
     int t = 0, skip = 0;
     // entry t + lane of the list: its r_low and the range of its children
@@ -278,53 +286,79 @@ __device__ __forceinline__ void for_source_batches(bool staged, const uint64_t *
             cnt = par_spl[src + 1] - s0;
         }
     };
-    load(0);
-    while (t < len) {
-        const float Rw = uni(rw());
+    // the prepared batch: nN children (0: the walk ends), indices in FI half
+    // `half`, the records of positions lane and lane + 64 as two halves each
+    int nN = 0, half = 0;
+    float4 r0a = make_float4(0, 0, 0, 0), r0b = r0a, r1a = r0a, r1b = r0a;
+    auto fetch_rec = [&](int x, float4 &ra, float4 &rb) {
+        const float4 *rec = reinterpret_cast<const float4 *>(nodes + x);
+        ra = rec[0];
+        rb = rec[1];
+        if (scnt) rb.w = __int_as_float(scnt[x]);  // Node.count is the last word
+    };
+    auto prepare = [&](float Rw) {
+        int *fi = FI + half * FCAP;
+        nN = 0;
+        if (t >= len) return;
         const int b0 = s0 + (lane == 0 ? skip : 0);
         const int c_all = cnt - (lane == 0 ? skip : 0);
         const bool ok = valid && (!staged || rl <= Rw);
         const uint64_t okm = __ballot(ok);  // sorted by r_low: a prefix of the lanes
         const int nok = ~okm ? __ffsll((unsigned long long)~okm) - 1 : 64;
-        if (nok == 0) break;
+        if (nok == 0) {
+            t = len;
+            return;
+        }
         const int c = lane < nok ? c_all : 0;
         const int incl = wave_incl_scan(c);
         const int ntake = __popcll(__ballot(lane < nok && incl <= FCAP));
-        int nF;
         if (ntake == 0) {
             // the first source alone overflows the buffer: take FCAP of its
             // children (the loaded entries stay those of position t)
             const int f0 = uni(__shfl(b0, 0, 64));
-            for (int f = lane; f < FCAP; f += 64) {
-                Node o = nodes[f0 + f];
-                if (scnt) o.count = scnt[f0 + f];
-                F[f] = o;
-                FI[f] = f0 + f;
-            }
-            nF = FCAP;
+            for (int f = lane; f < FCAP; f += 64) fi[f] = f0 + f;
+            nN = FCAP;
             skip += FCAP;
         } else {
-            // lane q < ntake lists the indices of its source's children;
-            // then every lane copies node records lane, lane + 64, ... (the
-            // loads are independent instead of one chain per source)
+            // lane q < ntake lists the indices of its source's children
             if (lane < ntake) {
                 const int off = incl - c;
-                for (int q = 0; q < c; ++q) FI[off + q] = b0 + q;
+                for (int q = 0; q < c; ++q) fi[off + q] = b0 + q;
             }
-            nF = uni(__shfl(incl, ntake - 1, 64));
-            wave_lds_sync();
-            for (int f = lane; f < nF; f += 64) {
-                const int fi = FI[f];
-                Node o = nodes[fi];
-                if (scnt) o.count = scnt[fi];
-                F[f] = o;
-            }
+            nN = uni(__shfl(incl, ntake - 1, 64));
             t += ntake;
             skip = 0;
-            load(t);
         }
         wave_lds_sync();
-        fn(nF);
+        // every lane loads records lane and lane + 64 (independent loads
+        // instead of one chain per source)
+        if (lane < nN) fetch_rec(fi[lane], r0a, r0b);
+        if (lane + 64 < nN) fetch_rec(fi[lane + 64], r1a, r1b);
+        if (ntake != 0) load(t);
+    };
+    auto commit = [&]() {
+        float4 *f4 = reinterpret_cast<float4 *>(F);
+        if (lane < nN) {
+            f4[2 * lane] = r0a;
+            f4[2 * lane + 1] = r0b;
+        }
+        if (lane + 64 < nN) {
+            f4[2 * lane + 128] = r1a;
+            f4[2 * lane + 129] = r1b;
+        }
+    };
+    load(0);
+    prepare(uni(rw()));
+    commit();
+    wave_lds_sync();
+    while (nN > 0) {
+        const int nF = nN;
+        const int *fcur = FI + half * FCAP;
+        half ^= 1;
+        prepare(uni(rw()));
+        fn(nF, fcur);
+        wave_lds_sync();
+        commit();
         wave_lds_sync();
     }
 }
@@ -377,9 +411,9 @@ __global__ __launch_bounds__(64 * WPB) void k_knn_step(
     int sort_cap, int presorted, const int *__restrict__ scnt, float Lp,
     float *__restrict__ rout) {
     // one block per wave: the staged list (LCAP entries), then the staged
-    // source children (FCAP records and their indices); before the walk the
+    // source children (FCAP records, and their indices for two batches); before the walk the
     // whole block is the scratch in which a longer list is sorted
-    constexpr int RAW = LCAP + FCAP * (int)(sizeof(Node) / 8) + FCAP / 2;
+    constexpr int RAW = LCAP + FCAP * (int)(sizeof(Node) / 8) + FCAP;
     __shared__ __align__(16) uint64_t s_raw[WPB][RAW];
     const int w = WPB == 1 ? 0 : uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
     // work item I: receiving parent it.x, its children from it.y (at most cb
@@ -421,7 +455,7 @@ __global__ __launch_bounds__(64 * WPB) void k_knn_step(
         for_source_batches(
             staged, L, gl, len, par_spl, nodes, scnt, F, FI,
             [&]() { return wave_max_f(act ? R : -INFINITY); },
-            [&](int nF) {
+            [&](int nF, const int *) {
                 for (int f = sl; f < nF; f += G) {
                     const Node o = F[f];
                     const float r = box_up2_m<PER>(me, o, Lp);
@@ -469,7 +503,7 @@ __global__ __launch_bounds__(64 * WPB) void k_knn_step(
         int cnt = 0;
         for_source_batches(
             staged, L, gl, len, par_spl, nodes, scnt, F, FI, [&]() { return Rw; },
-            [&](int nF) {
+            [&](int nF, const int *) {
                 for (int f = sl; f < nF; f += G) {
                     const Node o = F[f];
                     cnt += (act && o.count > 0 && box_low2_m<PER>(me, o, Lp) <= R) ? 1 : 0;
@@ -499,12 +533,12 @@ __global__ __launch_bounds__(64 * WPB) void k_knn_step(
         long long wp = (long long)base + (incl - cnt);
         for_source_batches(
             staged, L, gl, len, par_spl, nodes, scnt, F, FI, [&]() { return Rw; },
-            [&](int nF) {
+            [&](int nF, const int *fi) {
                 for (int f = sl; f < nF; f += G) {
                     const Node o = F[f];
                     const float lo = box_low2_m<PER>(me, o, Lp);
                     if (act && o.count > 0 && lo <= R) {
-                        list_out[wp] = make_int2(FI[f], __float_as_int(lo));
+                        list_out[wp] = make_int2(fi[f], __float_as_int(lo));
                         ++wp;
                     }
                 }
