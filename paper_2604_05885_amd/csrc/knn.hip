@@ -371,16 +371,26 @@ __device__ __forceinline__ void for_source_batches(bool staged, const uint64_t *
 // most WALK_CB.
 constexpr int WALK_CB = 8;
 constexpr int WALK_CB_UP = 2;
+// A parent whose list is longer than WALK_LONG entries takes items of at most
+// WALK_CB_LONG children: such items run many times longer than the rest and
+// would otherwise be the tail of the level.
+constexpr int WALK_LONG = 1024;
+constexpr int WALK_CB_LONG = 2;
+__device__ __forceinline__ int item_cb(int cb, int len) {
+    return len > WALK_LONG ? min(cb, WALK_CB_LONG) : cb;
+}
 
 __global__ __launch_bounds__(64) void k_walk_items(const int *__restrict__ par_spl, int n_par,
-                                                   int cb, int2 *__restrict__ items,
+                                                   int cb, const int2 *__restrict__ seg_in,
+                                                   int2 *__restrict__ items,
                                                    unsigned long long *__restrict__ count) {
     const int lane = lane_id();
     const int P = blockIdx.x * 64 + lane;
-    int c0 = 0, nb = 0;
+    int c0 = 0, nb = 0, cbe = cb;
     if (P < n_par) {
         c0 = par_spl[P];
-        nb = max(1, (par_spl[P + 1] - c0 + cb - 1) / cb);
+        cbe = item_cb(cb, seg_in[P].y);
+        nb = max(1, (par_spl[P + 1] - c0 + cbe - 1) / cbe);
     }
     const int incl = wave_incl_scan(nb);
     const int tot = uni(__shfl(incl, 63, 64));
@@ -388,7 +398,7 @@ __global__ __launch_bounds__(64) void k_walk_items(const int *__restrict__ par_s
     if (lane == 0) base = atomicAdd(count, (unsigned long long)tot);
     base = uni((unsigned long long)__shfl(base, 0, 64));
     for (int b = 0; b < nb; ++b)
-        items[base + (unsigned long long)(incl - nb + b)] = make_int2(P, c0 + b * cb);
+        items[base + (unsigned long long)(incl - nb + b)] = make_int2(P, c0 + b * cbe);
 }
 
 // Level step of the kNN walk: one wave per work item (a receiving parent and
@@ -416,8 +426,8 @@ __global__ __launch_bounds__(64 * WPB) void k_knn_step(
     constexpr int RAW = LCAP + FCAP * (int)(sizeof(Node) / 8) + FCAP;
     __shared__ __align__(16) uint64_t s_raw[WPB][RAW];
     const int w = WPB == 1 ? 0 : uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
-    // work item I: receiving parent it.x, its children from it.y (at most cb
-    // of them)
+    // work item I: receiving parent it.x, its children from it.y (at most
+    // item_cb(cb, list length) of them)
     const int I = xcd_block(blockIdx.x, gridDim.x) * WPB + w;
     if (I >= (int)uni(*n_items)) return;
     const int2 it = items[I];
@@ -425,7 +435,7 @@ __global__ __launch_bounds__(64 * WPB) void k_knn_step(
     const int2 sg = seg_in[P];
     int2 *gl = list_in + uni(sg.x);
     const int len = uni(sg.y);
-    const int c0 = uni(it.y), c1 = uni(min(par_spl[P + 1], it.y + cb));
+    const int c0 = uni(it.y), c1 = uni(min(par_spl[P + 1], it.y + item_cb(cb, len)));
     uint64_t *L = s_raw[w];
     Node *F = reinterpret_cast<Node *>(L + LCAP);
     int *FI = reinterpret_cast<int *>(L + LCAP + FCAP * (int)(sizeof(Node) / 8));
@@ -1174,7 +1184,8 @@ jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s,
     const int sort_max = t->opts.sort_max;
     const int walk_cap = LCAP, leaf_cap = std::min(sort_max, 1024);
     // work items of the walk (at most one per parent plus one per cb
-    // children): WALK_CB children per item at the leaf level, WALK_CB_UP
+    // children, or per WALK_CB_LONG children of a parent with a long list):
+    // WALK_CB children per item at the leaf level, WALK_CB_UP
     // above it, where there are few parents
     auto cb_of = [&](int p) {
         const int64_t n_par = p == P - 1 ? t->S : t->L[p + 1];
@@ -1182,7 +1193,7 @@ jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s,
     };
     auto item_bound = [&](int p) {
         const int64_t n_par = p == P - 1 ? t->S : t->L[p + 1];
-        return n_par + t->L[p] / cb_of(p) + 1;
+        return n_par + t->L[p] / std::min(cb_of(p), WALK_CB_LONG) + 1;
     };
     int64_t max_items = 0;
     for (int p = 0; p < P; ++p) max_items = std::max(max_items, item_bound(p));
@@ -1229,7 +1240,7 @@ jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s,
             if (!top) presort(list_in, seg_in, n_par, walk_cap, ctr + c_long + 2 * p);
             unsigned long long *n_items = ctr + c_items + p;
             k_walk_items<<<(unsigned)((n_par + 63) / 64), 64, 0, s>>>(
-                par_spl, (int)n_par, cb_of(p), d_items.as<int2>(), n_items);
+                par_spl, (int)n_par, cb_of(p), seg_in, d_items.as<int2>(), n_items);
             (per ? k_knn_step<true> : k_knn_step<false>)<<<blocks_for(item_bound(p), WPB),
                                                               64 * WPB, 0, s>>>(
                 d_items.as<int2>(), n_items, cb_of(p), seg_in, list_in, par_spl,
