@@ -135,6 +135,23 @@ __global__ __launch_bounds__(64) void k_find_long(const int2 *__restrict__ seg, 
     }
 }
 
+// The receivers whose lists are longer than min_len, in any order: the leaf
+// stage runs them first, so that these long waves overlap the rest of the
+// launch instead of trailing it.
+__global__ __launch_bounds__(64) void k_long_first(const int2 *__restrict__ seg, int n,
+                                                   int min_len, int *__restrict__ ids,
+                                                   unsigned long long *__restrict__ count) {
+    const int lane = lane_id();
+    const int i = blockIdx.x * 64 + lane;
+    const bool l = i < n && seg[i].y > min_len;
+    const uint64_t m = __ballot(l);
+    if (!m) return;
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(count, (unsigned long long)__popcll(m));
+    base = uni((unsigned long long)__shfl(base, 0, 64));
+    if (l) ids[base + __popcll(m & lanemask_lt())] = i;
+}
+
 // Bitonic sort of each listed segment by (r_low, source), in CAP keys of LDS,
 // by NW waves. A compare-exchange step of pair distance j touches, for pair
 // indices in one aligned range of PW = M / 2 / NW pairs, only the elements of
@@ -748,7 +765,8 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
     unsigned long long *__restrict__ stats, const unsigned long long *__restrict__ overflow,
     int sort_cap, int presorted, int out_stride, int col0, int kw,
     const int *__restrict__ scnt0, int src_hi, int qry_lo, float Lp,
-    const float *__restrict__ rleaf) {
+    const float *__restrict__ rleaf, const int *__restrict__ first,
+    const unsigned long long *__restrict__ n_first, int first_len) {
     // Lp: period of the cube (PER), Lh its half
     const float Lh = 0.5f * Lp;
     // one block per wave: the staged list (LCAP entries), the point tile,
@@ -762,9 +780,19 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
     __shared__ int s_offs[WPB][SB + 1];
     __shared__ int s_sc[WPB][SB];
     const int w = WPB == 1 ? 0 : uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
-    const int A = xcd_block(blockIdx.x, gridDim.x) * WPB + w;
+    // the first waves take the leaves with lists longer than first_len (in
+    // `first`), the others every leaf in order except those
+    const int wv = xcd_block(blockIdx.x, gridDim.x) * WPB + w;
+    const int nfirst = (int)uni(*n_first);
+    int A;
+    if (wv < nfirst) {
+        A = uni(first[wv]);
+    } else {
+        A = wv - nfirst;
+        if (A >= n_leaves || uni(seg[A].y) > first_len) return;
+    }
     // a level of this attempt overflowed (it is rerun): nothing to do
-    if (A >= n_leaves || *overflow) return;
+    if (*overflow) return;
     const Node a = leaves[A];
     uint64_t *L = s_raw[w];
     // The leaf's query points: all its points, or, with separate point types
@@ -1091,7 +1119,8 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
 
 typedef void (*leaf_fn)(const int2 *, int2 *, const Node *, const float4 *, int, const int *,
                         int32_t *, float *, unsigned long long *, const unsigned long long *, int,
-                        int, int, int, int, const int *, int, int, float, const float *);
+                        int, int, int, int, const int *, int, int, float, const float *,
+                        const int *, const unsigned long long *, int);
 
 template <int K, bool LO, bool PER>
 leaf_fn leaf_ptr() {
@@ -1168,7 +1197,8 @@ jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s,
     // walk level
     DBuf d_ctr;
     const size_t c_long = ctr_words(6), c_items = c_long + 2 * (JZ_MAX_PLANES + 1);
-    const size_t nctr = c_items + JZ_MAX_PLANES;
+    const size_t c_first = c_items + JZ_MAX_PLANES;  // leaves with long lists
+    const size_t nctr = c_first + 1;
     JZ_TRY(d_ctr.get(ac, nctr * sizeof(unsigned long long), s));
     unsigned long long *ctr = d_ctr.as<unsigned long long>();
     JZ_TRY(zero_words(ctr, nctr, s));
@@ -1199,9 +1229,10 @@ jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s,
     for (int p = 0; p < P; ++p) max_items = std::max(max_items, item_bound(p));
     DBuf d_items;
     JZ_TRY(d_items.get(ac, (size_t)max_items * sizeof(int2), s));
-    DBuf d_ids, d_rleaf;
+    DBuf d_ids, d_rleaf, d_first;
     JZ_TRY(d_ids.get(ac, 2 * (size_t)t->L[0] * sizeof(int), s));
     JZ_TRY(d_rleaf.get(ac, (size_t)t->L[0] * sizeof(float), s));
+    JZ_TRY(d_first.get(ac, (size_t)t->L[0] * sizeof(int), s));
     auto presort = [&](int2 *list, const int2 *seg, int64_t n, int min_len,
                        unsigned long long *count) {
         if (sort_max <= min_len) return;
@@ -1252,19 +1283,24 @@ jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s,
         }
         presort(lists[0].as<int2>(), segs[0].as<int2>(), t->L[0], leaf_cap,
                 ctr + c_long + 2 * JZ_MAX_PLANES);
+        k_long_first<<<(unsigned)((t->L[0] + 63) / 64), 64, 0, s>>>(
+            segs[0].as<int2>(), (int)t->L[0], leaf_cap, d_first.as<int>(), ctr + c_first);
         JZ_HIP(hipGetLastError());
+        // waves for every leaf plus the first ones (at most one per leaf_cap
+        // + 1 list entries)
+        const int64_t n_waves = t->L[0] + std::min<int64_t>(t->L[0], cap[0] / (leaf_cap + 1) + 1);
         if (ev.on) JZ_HIP(hipEventRecord(ev[1], s));
         // k <= 32: one pass; larger k: passes of 32 neighbours, each after
         // the last key of the one before
         for (int col = 0; col < k; col += 32) {
             const leaf_fn fn = leaf_kernel(k, col, per);
-            fn<<<blocks_for(t->L[0], WPB), 64 * WPB, 0, s>>>(
+            fn<<<blocks_for(n_waves, WPB), 64 * WPB, 0, s>>>(
                 segs[0].as<int2>(), lists[0].as<int2>(), t->nodes[0].as<Node>(),
                 t->pts4.as<float4>(), (int)t->L[0], t->nsets > 1 ? t->leaf_base.as<int>() : nullptr,
                 idx, dist2, ctr + CTR_STATS, ctr + CTR_FLAG, leaf_cap, sort_max, k, col,
                 std::min(32, k - col), joint ? t->src_cnt[0].as<int>() : nullptr,
                 joint ? (int)t->n_src : INT_MAX, joint ? (int)t->n_src : 0, period,
-                d_rleaf.as<float>());
+                d_rleaf.as<float>(), d_first.as<int>(), ctr + c_first, leaf_cap);
             JZ_HIP(hipGetLastError());
         }
         if (ev.on) JZ_HIP(hipEventRecord(ev[2], s));
