@@ -286,29 +286,10 @@ __device__ __forceinline__ int wave_sum_i(int v) {
     return v + swap32_i(v);
 }
 
-__device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
-__device__ __forceinline__ float wave_min(float v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
-__device__ __forceinline__ int wave_max_int(int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
-__device__ __forceinline__ int wave_sum(int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
+__device__ __forceinline__ float wave_max(float v) { return wave_max_f(v); }
+__device__ __forceinline__ float wave_min(float v) { return group_min_f(v, 64); }
+__device__ __forceinline__ int wave_max_int(int v) { return wave_max_i(v); }
+__device__ __forceinline__ int wave_sum(int v) { return wave_sum_i(v); }
 
 // inclusive prefix sum over the 64 lanes
 __device__ __forceinline__ int wave_incl_scan(int v) {
