@@ -30,9 +30,12 @@ __global__ void k_iota_n(int *__restrict__ a, int64_t n) {
     if (i < n) a[i] = (int)i;
 }
 
-__global__ void k_fill(int *__restrict__ a, int64_t n, int v) {
+// the smallest input index of every group starts as its root's own (a root is
+// a member; a point that stays a root of itself needs no update at all)
+__global__ __launch_bounds__(256) void k_init_min(const float4 *__restrict__ pts, int64_t n,
+                                                  int *__restrict__ minidx) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) a[i] = v;
+    if (i < n) minidx[i] = __float_as_int(pts[i].w);
 }
 
 __global__ void k_node_b2(const int *__restrict__ node_set, int64_t L,
@@ -395,7 +398,9 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_fof(
 // and the smallest input index per root. Points of one group are mostly
 // contiguous in z-order: the wave takes the minimum over each run of lanes
 // with the same root (a segmented scan, 6 steps whatever the number of runs)
-// and the last lane of a run issues one atomic for it.
+// and the last lane of a run issues one atomic for it, unless the root's
+// current minimum is already no larger (values only decrease, so one read
+// through the caches, even an older one, never skips a needed update).
 __global__ __launch_bounds__(256) void k_flatten_min(int *__restrict__ uf,
                                                      const float4 *__restrict__ pts, int64_t n,
                                                      int *__restrict__ minidx) {
@@ -428,7 +433,7 @@ __global__ __launch_bounds__(256) void k_flatten_min(int *__restrict__ uf,
     }
     const int next_root = __shfl_down(root, 1, 64);
     const bool tail = lane == 63 || next_root != root;
-    if (valid && tail) atomicMin(minidx + root, v);
+    if (valid && tail && v < ld_cached(minidx + root)) atomicMin(minidx + root, v);
 }
 
 __global__ void k_labels(const int *__restrict__ uf, const float4 *__restrict__ pts, int64_t n,
@@ -504,7 +509,7 @@ jz_status run_fof(jz_tree *t, const float *b2_set_host, int32_t *label, hipStrea
         JZ_HIP(hipMemsetAsync(ctr, 0, d_ctr.bytes, s));
         if (ev.on) JZ_HIP(hipEventRecord(ev[0], s));
         k_iota_n<<<blocks_for(n, 256), 256, 0, s>>>(d_uf.as<int>(), n);
-        k_fill<<<blocks_for(n, 256), 256, 0, s>>>(d_min.as<int>(), n, INT_MAX);
+        k_init_min<<<blocks_for(n, 256), 256, 0, s>>>(t->pts4.as<float4>(), n, d_min.as<int>());
         for (int p = P - 1; p >= 0; --p) {
             const bool top = p == P - 1;
             const int2 *seg_in = top ? t->fof_top_seg.as<int2>() : segs[p + 1].as<int2>();
