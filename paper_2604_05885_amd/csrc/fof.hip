@@ -77,7 +77,8 @@ __global__ __launch_bounds__(64 * WPB) void k_fof_l2p(const Node *__restrict__ l
     for (int i = a.start + 1 + lane; i < a.start + a.count; i += 64) uf[i] = a.start;
 }
 
-enum PairCase { kDiscard = 0, kLinked = 1, kDescend = 2 };
+// kConnected: within reach but both nodes are whole and already one group
+enum PairCase { kDiscard = 0, kLinked = 1, kDescend = 2, kConnected = 3 };
 
 template <bool PER>
 __device__ __forceinline__ int fof_case(const Node &me, int c, const Node &o, int s, float bb,
@@ -88,7 +89,7 @@ __device__ __forceinline__ int fof_case(const Node &me, int c, const Node &o, in
     // through the caches may be older, which only costs a redundant union)
     if (ld_cached(whole + c) && ld_cached(whole + s) &&
         uf_find_c(uf, me.start) == uf_find_c(uf, o.start))
-        return kDiscard;
+        return box_up2_m<PER>(me, o, L) <= bb ? kLinked : kConnected;
     if (box_up2_m<PER>(me, o, L) <= bb) {
         if (do_link) {
             uf_union_c(uf, me.start, o.start);
@@ -100,10 +101,15 @@ __device__ __forceinline__ int fof_case(const Node &me, int c, const Node &o, in
     return kDescend;
 }
 
-// Node walk step: one wave per receiving parent, lanes over its children.
-// Pass A links and counts the pairs to descend into; pass B re-evaluates and
-// writes them (the group state only merges between the passes, so pass B
-// emits a subset of what pass A counted; the segment length is what it wrote).
+// Node walk step: one wave per receiving parent; its children are spread over
+// the lanes with G = 64 / (children, rounded up to a power of 2) lanes per
+// child, the G lanes of a child splitting the staged source children between
+// them. Pass A links, and counts the pairs that geometry alone sends down
+// (within reach, not wholly within b); pass B re-evaluates them and writes
+// those still to be descended into: the group state only merges, so pass B
+// writes a subset of what pass A counted, whatever either pass read of it.
+// A child's entries are placed through a counter in LDS, so its list is one
+// contiguous run whichever of its lanes found them.
 template <bool PER>
 __global__ __launch_bounds__(64 * WPB) void k_fof_step(
     const int2 *__restrict__ seg_in, const int2 *__restrict__ list_in,
@@ -112,6 +118,7 @@ __global__ __launch_bounds__(64 * WPB) void k_fof_step(
     int2 *__restrict__ seg_out, int2 *__restrict__ list_out,
     unsigned long long *__restrict__ ctr, long long cap, unsigned long long *overflow, float L) {
     __shared__ Node s_tile[WPB][64];
+    __shared__ int s_emit[WPB][64];
     const int w = WPB == 1 ? 0 : uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
     const int P = xcd_block(blockIdx.x, gridDim.x) * WPB + w;
     if (P >= n_par) return;
@@ -120,11 +127,18 @@ __global__ __launch_bounds__(64 * WPB) void k_fof_step(
     const int len = uni(sg.y);
     const int c0 = uni(par_spl[P]), c1 = uni(par_spl[P + 1]);
     Node *tile = s_tile[w];
+    int *emit = s_emit[w];
     for (int cb = c0; cb < c1; cb += 64) {
-        const int c = cb + lane;
-        const bool act = c < c1;
-        const Node me = nodes[act ? c : c0];
-        const float bb = b2n ? b2n[act ? c : c0] : b2;
+        const int nc = min(64, c1 - cb);
+        // G = largest power of two with nc * G <= 64
+        int lg = 0;
+        while ((nc << (lg + 1)) <= 64) ++lg;
+        const int G = 1 << lg;
+        const int ci = lane >> lg, sl = lane & (G - 1);
+        const bool act = ci < nc;
+        const int c = cb + (act ? ci : 0);
+        const Node me = nodes[c];
+        const float bb = b2n ? b2n[c] : b2;
         int cnt = 0;
         for (int t = 0; t < len; ++t) {
             const int S = gl[t].x;
@@ -133,15 +147,18 @@ __global__ __launch_bounds__(64 * WPB) void k_fof_step(
                 const int ns = min(64, s1 - sb);
                 if (lane < ns) tile[lane] = nodes[sb + lane];
                 wave_lds_sync();
-                for (int j = 0; j < ns; ++j) {
+                for (int j = sl; j < ns; j += G) {
                     const int s = sb + j;
                     if (!act || s < c) continue;
                     float lo;
-                    if (fof_case<PER>(me, c, tile[j], s, bb, whole, uf, true, lo, L) == kDescend) ++cnt;
+                    const int k = fof_case<PER>(me, c, tile[j], s, bb, whole, uf, true, lo, L);
+                    cnt += (k == kDescend || k == kConnected) ? 1 : 0;
                 }
                 wave_lds_sync();
             }
         }
+        // reserve: lanes are child-major, so a wave scan gives each child a
+        // contiguous segment
         const int incl = wave_incl_scan(cnt);
         const int total = uni(__shfl(incl, 63, 64));
         // segment in arena P % LIST_ARENAS (cap entries each)
@@ -150,15 +167,20 @@ __global__ __launch_bounds__(64 * WPB) void k_fof_step(
         if (lane == 0) lb = atomicAdd(ctr + ar, (unsigned long long)total);
         lb = uni((unsigned long long)__shfl(lb, 0, 64));
         const unsigned long long base = (unsigned long long)ar * (unsigned long long)cap + lb;
-        const long long pos = (long long)base + (incl - cnt);
         const bool ok = (long long)lb + total <= cap;
+        const int gfirst = ci << lg;
+        const int gstart = __shfl(incl - cnt, gfirst & 63, 64);
+        const int gend = __shfl(incl, (gfirst + G - 1) & 63, 64);
         if (!ok) {
             // lists below are incomplete: the leaf stage of this attempt exits
             if (lane == 0) *overflow = 1;
-            if (act) seg_out[c] = make_int2(0, 0);
+            if (act && sl == 0) seg_out[c] = make_int2(0, 0);
             continue;
         }
-        int emitted = 0;
+        const long long cpos = (long long)base + gstart;
+        const int room = gend - gstart;
+        emit[lane] = 0;
+        wave_lds_sync();
         for (int t = 0; t < len; ++t) {
             const int S = gl[t].x;
             const int s0 = par_spl[S], s1 = par_spl[S + 1];
@@ -166,19 +188,20 @@ __global__ __launch_bounds__(64 * WPB) void k_fof_step(
                 const int ns = min(64, s1 - sb);
                 if (lane < ns) tile[lane] = nodes[sb + lane];
                 wave_lds_sync();
-                for (int j = 0; j < ns; ++j) {
+                for (int j = sl; j < ns; j += G) {
                     const int s = sb + j;
-                    if (!act || s < c || emitted >= cnt) continue;
+                    if (!act || s < c) continue;
                     float lo;
                     if (fof_case<PER>(me, c, tile[j], s, bb, whole, uf, false, lo, L) == kDescend) {
-                        list_out[pos + emitted] = make_int2(s, __float_as_int(lo));
-                        ++emitted;
+                        const int k = atomicAdd(emit + ci, 1);
+                        if (k < room) list_out[cpos + k] = make_int2(s, __float_as_int(lo));
                     }
                 }
                 wave_lds_sync();
             }
         }
-        if (act) seg_out[c] = make_int2((int)pos, emitted);
+        if (act && sl == 0) seg_out[c] = make_int2((int)cpos, min(emit[ci], room));
+        wave_lds_sync();
     }
 }
 
