@@ -93,9 +93,11 @@ def test_config_2p27_k32(jz):
         del lab
     del d
     rows = np.random.default_rng(27).choice(n, 2 ** 11, replace=False)
-    ridx = torch.from_numpy(rows).cuda()
-    knn_rows_equal(idx[ridx].cpu().numpy(), d2[ridx].cpu().numpy(), rows, p, 32, "2^27 k=32")
-    say("brute-force rows %.1fs" % (time.time() - t0))
+    for r0 in range(0, rows.size, 256):
+        rs = rows[r0:r0 + 256]
+        ridx = torch.from_numpy(rs).cuda()
+        knn_rows_equal(idx[ridx].cpu().numpy(), d2[ridx].cpu().numpy(), rs, p, 32, "2^27 k=32")
+        say("brute-force rows %d %.1fs" % (r0 + rs.size, time.time() - t0))
     chunk = 1 << 22
     with oracle.KdTree(p) as kd:
         say("kd-tree %.1fs" % (time.time() - t0))
