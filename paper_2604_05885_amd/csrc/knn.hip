@@ -843,9 +843,11 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
     for (int i = 0; i < K; ++i) best.set(i, pad);
     unsigned evals = 0, visited = 0, rounds = 0, steps = 0;
     // candidate queue of this lane: positions at q0, q0 + 64, ... up to qp
-    uint8_t *const q0 = reinterpret_cast<uint8_t *>(L + O_Q) + lane;
-    uint8_t *qp = q0;
-    const uint8_t *const qlim = q0 + 64 * (CQ - CH);
+    // (LDS-typed pointers: 32-bit arithmetic instead of 64-bit)
+    typedef __attribute__((address_space(3))) uint8_t lds_u8;
+    lds_u8 *const q0 = (lds_u8 *)(reinterpret_cast<uint8_t *>(L + O_Q) + lane);
+    lds_u8 *qp = q0;
+    const lds_u8 *const qlim = q0 + 64 * (CQ - CH);
 
     // the group's k-th distance: an upper bound of the query's final k-th
     // the walk's radius of this leaf: the k-th distance of each of its
