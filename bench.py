@@ -309,7 +309,8 @@ def batched(args):
         "points_per_s": n / t_batched,
         "identical_to_plain": same,
         "forest_stats": {kk: v for kk, v in st.items() if kk in ("planes", "nodes", "super_nodes")},
-        "autotuned": {"leaf_max": opts.leaf_max, "coarsen": opts.coarsen},
+        "autotuned": {"leaf_max": opts.leaf_max, "coarsen": opts.coarsen,
+                      "n_target": opts.n_target, "ngr": opts.ngr},
     }
     print(json.dumps(out), flush=True)
 

@@ -234,15 +234,24 @@ JZ_API jz_status jz_fof_catalogue(jz_tree *t, float b, int min_members, const fl
 
 /* ---- autotuning -----------------------------------------------------------
  * Time the build plus the requested operations on the caller's workload for
- * each candidate setting (leaf_max in {32, 48, 64} x coarsen in {4, 8}; other
- * fields taken from *base or the defaults) and return the fastest in *best
- * and its time (ms, best of two runs) in *best_ms. points / offsets / nsets
- * as for jz_forest_build (offsets may be NULL for one set of n points; then
- * nsets is n). k in [1, JZ_MAX_K] runs kNN, k = 0 skips it; b (HOST, one value per
- * set) runs FoF, NULL skips it. The winner is remembered for the signature
- * (k, FoF or not, number of sets, log2 of the point count) for the rest of
- * the process, and later calls with that signature return it without
- * timing. Results of the method never depend on these options. */
+ * each candidate setting and return the fastest in *best and its time (ms,
+ * best of two runs) in *best_ms. Candidates: leaf_max in {32, 48, 64} x
+ * coarsen in {4, 8, 16}, then, from the best of those, n_target in {500,
+ * 2000} and then ngr in {16, 64}; other fields are taken from *base or the
+ * defaults. (A leaf is one wave of queries, so leaves hold at most 64 points;
+ * leaves of up to 16 or 32 points get 4 or 2 lanes per query by themselves.)
+ * points / offsets / nsets as for jz_forest_build (offsets may be NULL for one
+ * set of n points; then nsets is n). k in [1, JZ_MAX_K] runs kNN, k = 0 skips
+ * it; b (HOST, one value per set) runs FoF, NULL skips it. The winner is
+ * remembered for the signature (device architecture, k, FoF or not, number
+ * of sets, log2 of the point count) for the rest of the process, and later
+ * calls with that signature return it without timing. If the environment
+ * variable JZ_TUNE_CACHE names a file, winners are also appended to it as one
+ * JSON object per line ({"arch", "k", "fof", "sets", "log2n", "leaf_max",
+ * "coarsen", "n_target", "ngr", "ms"}), and a signature not yet tuned in this
+ * process is looked up there first (the last matching line wins; lines whose
+ * options are out of range are ignored). Results of the method never depend on
+ * these options. */
 JZ_API jz_status jz_autotune(const float *points, const int64_t *offsets, int64_t nsets,
                              int k, const float *b, void *stream, const jz_build_opts *base,
                              jz_build_opts *best, double *best_ms);
@@ -250,10 +259,13 @@ JZ_API jz_status jz_autotune(const float *points, const int64_t *offsets, int64_
 /* ---- serving: a continuous-batching request loop -----------------------
  * Requests (kNN or FoF on their own point sets) are submitted at any time from
  * any thread. Worker threads, each with its own HIP stream, repeatedly take
- * the oldest pending request and every later pending request of the same
- * kind (same op, same k), as far as the device-memory budget and the batch
- * caps allow, solve them as one forest (one sort, one set of launches), and
- * copy each result to its request's output buffers. Requests that arrive
+ * the oldest pending request that fits the free part of the device-memory
+ * budget and every later pending request of the same kind (same op, same k),
+ * as far as the budget and the batch caps allow, solve them as one forest
+ * (one sort, one set of launches), and copy each result to its request's
+ * output buffers. The oldest pending request may be passed over this way by
+ * later ones at most 8 times; after that no batch starts until it fits (no
+ * request waits forever behind smaller ones). Requests that arrive
  * while batches run join the next batch a worker forms; batches on different
  * streams overlap on the device. Each result is identical to what
  * jz_build + jz_knn / jz_fof give for that request alone. */

@@ -225,6 +225,8 @@ struct DeviceGuard {
     }
 };
 
+}  // namespace
+
 jz_status check_opts(const jz_build_opts &o) {
     if (o.leaf_max < 1 || o.leaf_max > 64) return jz_fail(JZ_E_INVALID, "leaf_max must be in [1, 64]");
     if (o.coarsen < 2 || o.coarsen > 64) return jz_fail(JZ_E_INVALID, "coarsen must be in [2, 64]");
@@ -241,8 +243,6 @@ jz_status check_opts(const jz_build_opts &o) {
         return jz_fail(JZ_E_INVALID, "reg_fmax must be finite and >= 0");
     return JZ_OK;
 }
-
-}  // namespace
 
 jz_status tree_create(const float *points, const int64_t *offsets, int nsets, hipStream_t s,
                       const jz_build_opts *opts, const jz_allocator *alloc, jz_tree **out) {

@@ -1,11 +1,13 @@
 // Continuous-batching request loop (jz_server_* in include/jz.h).
 //
 // Submitted requests wait in one FIFO queue. Each worker thread owns a HIP
-// stream; when free it takes the oldest request and every later pending
-// request of the same kind (op, k) while the device-memory budget and the
-// batch caps allow, solves them as one forest (one sort, one launch per
-// stage for all of them), copies each result to its request's buffers, and
-// marks the requests done with a completion time. Requests arriving during a
+// stream; when free it takes the oldest request that fits the free part of
+// the device-memory budget and every later pending request of the same kind
+// (op, k) while the budget and the batch caps allow, solves them as one
+// forest (one sort, one launch per stage for all of them), copies each result
+// to its request's buffers, and marks the requests done with a completion
+// time. The oldest request may be passed over by later, smaller ones at most
+// MAX_BYPASS times; then the workers wait until it fits. Requests arriving during a
 // batch join the next batch a worker forms, and batches of different workers
 // overlap on the device. Sets in a forest never interact and every result is
 // exact, so a request's result does not depend on the batch it ran in.
@@ -41,7 +43,11 @@ struct Req {
     jz_status status = JZ_OK;
     std::string msg;  // the worker's error message when status != JZ_OK
     int64_t t_done = 0;
+    int bypassed = 0;  // batches started ahead of it while it was the oldest
 };
+
+constexpr int MAX_BYPASS = 8;     // times the oldest request may be passed over
+constexpr int ADMIT_WINDOW = 64;  // pending requests looked at for one that fits
 
 // Device bytes a request adds to a batch (an upper estimate): the tree build
 // (input copy, keys and values twice, sorted float4 copy, planes) about 150 B
@@ -173,9 +179,24 @@ jz_status run_batch(jz_server *S, const std::vector<Req *> &batch, hipStream_t s
     return st;
 }
 
-bool can_start(const jz_server *S) {
-    return !S->pending.empty() && S->pending.front()->bytes <= S->o.hbm_budget - S->in_use;
+// The request a new batch starts from: the oldest that fits the free budget
+// (within the first ADMIT_WINDOW), unless the oldest has been passed over
+// MAX_BYPASS times already; nullptr if none may start now.
+Req *first_fit(const jz_server *S) {
+    if (S->pending.empty()) return nullptr;
+    const size_t avail = S->o.hbm_budget - S->in_use;
+    Req *head = S->pending.front();
+    if (head->bytes <= avail) return head;
+    if (head->bypassed >= MAX_BYPASS) return nullptr;
+    int scanned = 0;
+    for (Req *q : S->pending) {
+        if (++scanned > ADMIT_WINDOW) break;
+        if (q->bytes <= avail) return q;
+    }
+    return nullptr;
 }
+
+bool can_start(const jz_server *S) { return first_fit(S) != nullptr; }
 
 void worker(jz_server *S) {
     (void)hipSetDevice(S->device);
@@ -188,9 +209,11 @@ void worker(jz_server *S) {
     for (;;) {
         S->cv_work.wait(lk, [&] { return can_start(S) || (S->stop && S->pending.empty()); });
         if (S->pending.empty()) break;  // stopping and drained
-        // the oldest request and the later ones of the same kind that fit
+        // the oldest request that fits and the later ones of the same kind
+        // that fit too
         std::vector<Req *> batch;
-        const Req *head = S->pending.front();
+        const Req *head = first_fit(S);
+        if (head != S->pending.front()) S->pending.front()->bypassed++;
         const size_t avail = S->o.hbm_budget - S->in_use;
         size_t bytes = 0;
         int64_t pts = 0;

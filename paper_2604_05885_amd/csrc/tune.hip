@@ -1,10 +1,16 @@
 // Autotuner (jz_autotune in include/jz.h): times candidate tree options on the
-// caller's workload and remembers the fastest per workload signature.
+// caller's workload and remembers the fastest per workload signature, in the
+// process and, when JZ_TUNE_CACHE names a file, in that file (one JSON object
+// per line), so that later processes reuse it.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
 #include <map>
 #include <mutex>
+#include <string>
 #include <tuple>
 #include <vector>
 
@@ -12,9 +18,74 @@
 
 namespace {
 
-using Sig = std::tuple<int, int, int64_t, int>;  // k, FoF, sets, log2 n
+using Sig = std::tuple<std::string, int, int, int64_t, int>;  // arch, k, FoF, sets, log2 n
 std::mutex g_tune_m;
 std::map<Sig, std::pair<jz_build_opts, double>> g_tuned;
+
+std::string device_arch(int dev) {
+    hipDeviceProp_t pr;
+    if (hipGetDeviceProperties(&pr, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return "unknown";
+    }
+    std::string a = pr.gcnArchName;
+    const size_t c = a.find(':');
+    return c == std::string::npos ? a : a.substr(0, c);
+}
+
+const char *cache_path() {
+    const char *p = std::getenv("JZ_TUNE_CACHE");
+    return p && *p ? p : nullptr;
+}
+
+// the cached entry for sig in the file, if any (the last matching line wins)
+bool cache_lookup(const Sig &sig, const jz_build_opts &o0, jz_build_opts *o, double *ms) {
+    const char *path = cache_path();
+    if (!path) return false;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    bool found = false;
+    while (std::fgets(line, sizeof line, f)) {
+        char arch[32] = {0};
+        int k = 0, fof = 0, lg = 0, leaf = 0, coarsen = 0, nt = 0, ngr = 0;
+        long long sets = 0;
+        double t = 0;
+        if (std::sscanf(line,
+                        "{\"arch\":\"%31[^\"]\",\"k\":%d,\"fof\":%d,\"sets\":%lld,\"log2n\":%d,"
+                        "\"leaf_max\":%d,\"coarsen\":%d,\"n_target\":%d,\"ngr\":%d,\"ms\":%lf}",
+                        arch, &k, &fof, &sets, &lg, &leaf, &coarsen, &nt, &ngr, &t) != 10)
+            continue;
+        if (Sig{arch, k, fof, (int64_t)sets, lg} != sig) continue;
+        jz_build_opts c = o0;
+        c.leaf_max = leaf;
+        c.coarsen = coarsen;
+        c.n_target = nt;
+        c.ngr = ngr;
+        if (check_opts(c) != JZ_OK) continue;
+        *o = c;
+        *ms = t;
+        found = true;
+    }
+    std::fclose(f);
+    return found;
+}
+
+void cache_store(const Sig &sig, const jz_build_opts &o, double ms) {
+    const char *path = cache_path();
+    if (!path) return;
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;
+    char line[512];
+    std::snprintf(line, sizeof line,
+                  "{\"arch\":\"%s\",\"k\":%d,\"fof\":%d,\"sets\":%lld,\"log2n\":%d,"
+                  "\"leaf_max\":%d,\"coarsen\":%d,\"n_target\":%d,\"ngr\":%d,\"ms\":%.6f}\n",
+                  std::get<0>(sig).c_str(), std::get<1>(sig), std::get<2>(sig),
+                  (long long)std::get<3>(sig), std::get<4>(sig), o.leaf_max, o.coarsen, o.n_target,
+                  o.ngr, ms);
+    std::fputs(line, f);  // one write per line: appends from several processes do not interleave
+    std::fclose(f);
+}
 
 // one timed run: build + kNN and/or FoF; returns device time in ms
 jz_status time_once(const float *points, const std::vector<int64_t> &off, int k,
@@ -76,22 +147,29 @@ extern "C" jz_status jz_autotune(const float *points, const int64_t *offsets, in
             b2[i] = b[i] * b[i];
         }
     }
-    const Sig sig{k, b ? 1 : 0, (int64_t)sets, n > 0 ? (int)std::floor(std::log2((double)n)) : 0};
+    jz_build_opts o0;
+    jz_default_opts(&o0);
+    if (base) o0 = *base;
+    JZ_TRY(check_opts(o0));
+    int dev = 0;
+    JZ_HIP(hipGetDevice(&dev));
+    const Sig sig{device_arch(dev), k, b ? 1 : 0, (int64_t)sets,
+                  n > 0 ? (int)std::floor(std::log2((double)n)) : 0};
     {
         std::lock_guard<std::mutex> lk(g_tune_m);
         auto it = g_tuned.find(sig);
+        if (it == g_tuned.end()) {
+            jz_build_opts c;
+            double t = 0;
+            if (cache_lookup(sig, o0, &c, &t)) it = g_tuned.emplace(sig, std::make_pair(c, t)).first;
+        }
         if (it != g_tuned.end()) {
             *best = it->second.first;
             if (best_ms) *best_ms = it->second.second;
             return JZ_OK;
         }
     }
-    jz_build_opts o0;
-    jz_default_opts(&o0);
-    if (base) o0 = *base;
     hipStream_t s = (hipStream_t)stream;
-    int dev = 0;
-    JZ_HIP(hipGetDevice(&dev));
     AllocCtx ac;
     ac.device = dev;
     DBuf oi, od, ol;
@@ -102,27 +180,48 @@ extern "C" jz_status jz_autotune(const float *points, const int64_t *offsets, in
     if (b) JZ_TRY(ol.get(&ac, (size_t)n * sizeof(int32_t), s));
     double bestt = INFINITY;
     jz_build_opts bo = o0;
+    // best of two timed runs of each candidate
+    auto try_opts = [&](const jz_build_opts &o) -> jz_status {
+        double tmin = INFINITY;
+        for (int rep = 0; rep < 2; ++rep) {
+            double ms = 0;
+            JZ_TRY(time_once(points, off, k, b2, s, o, oi.as<int32_t>(), od.as<float>(),
+                             ol.as<int32_t>(), &ms));
+            tmin = std::min(tmin, ms);
+        }
+        if (tmin < bestt) {
+            bestt = tmin;
+            bo = o;
+        }
+        return JZ_OK;
+    };
+    // leaf size x coarsening on a grid (a leaf is one wave of queries, so
+    // at most 64 points), then the stop rule of the planes and the super-node
+    // width around the best of those
     for (int leaf : {32, 48, 64}) {
-        for (int c : {4, 8}) {
+        for (int c : {4, 8, 16}) {
             jz_build_opts o = o0;
             o.leaf_max = leaf;
             o.coarsen = c;
-            double tmin = INFINITY;
-            for (int rep = 0; rep < 2; ++rep) {
-                double ms = 0;
-                JZ_TRY(time_once(points, off, k, b2, s, o, oi.as<int32_t>(), od.as<float>(),
-                                 ol.as<int32_t>(), &ms));
-                tmin = std::min(tmin, ms);
-            }
-            if (tmin < bestt) {
-                bestt = tmin;
-                bo = o;
-            }
+            JZ_TRY(try_opts(o));
         }
+    }
+    const jz_build_opts grid_best = bo;
+    for (int nt : {500, 2000}) {
+        jz_build_opts o = grid_best;
+        o.n_target = nt;
+        JZ_TRY(try_opts(o));
+    }
+    const jz_build_opts nt_best = bo;
+    for (int g : {16, 64}) {
+        jz_build_opts o = nt_best;
+        o.ngr = g;
+        JZ_TRY(try_opts(o));
     }
     {
         std::lock_guard<std::mutex> lk(g_tune_m);
         g_tuned[sig] = {bo, bestt};
+        cache_store(sig, bo, bestt);
     }
     *best = bo;
     if (best_ms) *best_ms = bestt;

@@ -1,6 +1,8 @@
 """GPU tests of the continuous-batching server (through the C ABI): every
 request's result equals its standalone result and the oracle, whatever batch
 it ran in."""
+import json
+
 import numpy as np
 import pytest
 
@@ -93,12 +95,59 @@ def test_server_budget(jz):
         assert e.value.status == jz.JZ_E_UNSUPPORTED
 
 
+def test_autotune_cache_file(jz, tmp_path, monkeypatch):
+    """Winners are appended to the JZ_TUNE_CACHE file, and a signature not yet
+    tuned in this process is taken from the file without timing."""
+    path = tmp_path / "tune.jsonl"
+    monkeypatch.setenv("JZ_TUNE_CACHE", str(path))
+    p = inputs.clustered(5000, 8, 78)
+    d = torch.from_numpy(p).cuda()
+    opts, ms = jz.jz_autotune(d, k=5)
+    lines = path.read_text().splitlines()
+    assert len(lines) == 1
+    e = json.loads(lines[0])
+    assert (e["k"], e["fof"], e["sets"], e["log2n"]) == (5, 0, 1, 12)
+    assert (e["leaf_max"], e["coarsen"], e["n_target"], e["ngr"]) == (
+        opts.leaf_max, opts.coarsen, opts.n_target, opts.ngr)
+    # a hand-written entry for another signature is used as it stands
+    e2 = dict(e, k=6, leaf_max=48, coarsen=16, n_target=500, ngr=16, ms=12.5)
+    with open(path, "a") as f:
+        f.write(json.dumps(e2, separators=(",", ":")) + "\n")
+    got, ms2 = jz.jz_autotune(d, k=6)
+    assert (got.leaf_max, got.coarsen, got.n_target, got.ngr, ms2) == (48, 16, 500, 16, 12.5)
+
+
+def test_server_admits_a_later_request_that_fits(jz):
+    """With a budget the oldest request cannot get while another batch holds
+    part of it, a later small request starts ahead of it; every result is
+    still the standalone one."""
+    big = torch.from_numpy(inputs.uniform(60000, 31)).cuda()
+    small = torch.from_numpy(inputs.uniform(2000, 32)).cuda()
+    torch.cuda.synchronize()
+    with jz.jz_build(big) as t:
+        wi, wd = t.knn(8)
+    with jz.jz_build(small) as t:
+        si, sd = t.knn(8)
+    torch.cuda.synchronize()
+    # budget: one big request (about 214 B per point plus 1 MiB) plus a few
+    # small ones, but not two big ones
+    budget = int(60000 * 300 + (1 << 21) * 3)
+    with jz.Server(hbm_budget=budget, streams=2) as S:
+        ts = [S.submit_knn(big, 8), S.submit_knn(big, 8)] + [S.submit_knn(small, 8) for _ in range(6)]
+        res = [S.wait(x)[0] for x in ts]
+    for r in res[:2]:
+        assert torch.equal(r[0], wi) and torch.equal(r[1], wd)
+    for r in res[2:]:
+        assert torch.equal(r[0], si) and torch.equal(r[1], sd)
+
+
 def test_autotune_picks_valid_options(jz):
     p = inputs.clustered(30000, 16, 77)
     d = torch.from_numpy(p).cuda()
     b = inputs.linking_length(30000)
     opts, ms = jz.jz_autotune(d, k=8, b=b)
-    assert opts.leaf_max in (32, 48, 64) and opts.coarsen in (4, 8) and ms > 0
+    assert opts.leaf_max in (32, 48, 64) and opts.coarsen in (4, 8, 16) and ms > 0
+    assert opts.n_target in (500, 1000, 2000) and opts.ngr in (16, 32, 64)
     again, ms2 = jz.jz_autotune(d, k=8, b=b)  # remembered
     assert (again.leaf_max, again.coarsen, ms2) == (opts.leaf_max, opts.coarsen, ms)
     with jz.jz_build(d, opts) as t:
