@@ -329,13 +329,27 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_fof(
         // source's box) and pops its own chunks, so a pass costs the largest
         // per-lane chunk count, not the number of chunks any lane needs.
         const int nch = uni(npts >> 3);
-        unsigned M = 0;
+        // periodic box: a chunk whose rounded differences to this point stay
+        // within half a period on every axis (fl(q - lo) <= h, fl(q - hi) >=
+        // -h; the rounded difference is monotone) never wraps, and its bound
+        // and distances are the open ones bit for bit; W marks the others,
+        // and the periodic forms run only where some lane has one
+        unsigned M = 0, W = 0;
         for (int c = 0; c < nch; ++c) {
             const float4 *bx = cbox + c * 2;
             const float4 blo = bx[0], bhi = bx[1];
-            const float lo2 = point_low2_m<PER>(me.x, me.y, me.z, blo.x, blo.y, blo.z, bhi.x, bhi.y,
-                                                bhi.z, L);
-            M |= (act && lo2 <= bb) ? (1u << c) : 0u;
+            bool wrap = false;
+            if constexpr (PER)
+                wrap = !(me.x - blo.x <= Lh && me.x - bhi.x >= -Lh && me.y - blo.y <= Lh &&
+                         me.y - bhi.y >= -Lh && me.z - blo.z <= Lh && me.z - bhi.z >= -Lh);
+            const float lo2 =
+                (PER && __ballot(act && wrap))
+                    ? point_low2_m<PER>(me.x, me.y, me.z, blo.x, blo.y, blo.z, bhi.x, bhi.y, bhi.z, L)
+                    : point_low2_m<false>(me.x, me.y, me.z, blo.x, blo.y, blo.z, bhi.x, bhi.y, bhi.z,
+                                          L);
+            const bool need = act && lo2 <= bb;
+            M |= need ? (1u << c) : 0u;
+            W |= need && wrap ? (1u << c) : 0u;
         }
         uint64_t lk[FTILE / 64] = {};
         const int nit = uni(wave_max_i(__popc(M)));
@@ -346,12 +360,19 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_fof(
             const int real = has ? __float_as_int(cbox[c * 2].w) : 0;
             const int cfirst = __float_as_int(cbox[c * 2 + 1].w);
             unsigned m8 = 0;
+            auto eval = [&](auto per_const) {
+                constexpr bool P = decltype(per_const)::value;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const float4 s = tile[fslot(c * 8 + u)];
-                const float dd = dist2_m<PER>(me.x, me.y, me.z, s.x, s.y, s.z, L, Lh);
-                m8 |= (u < real && cfirst + u > my && dd <= bb) ? (1u << u) : 0u;
-            }
+                for (int u = 0; u < 8; ++u) {
+                    const float4 s = tile[fslot(c * 8 + u)];
+                    const float dd = dist2_m<P>(me.x, me.y, me.z, s.x, s.y, s.z, L, Lh);
+                    m8 |= (u < real && cfirst + u > my && dd <= bb) ? (1u << u) : 0u;
+                }
+            };
+            if (PER && __ballot(has && ((W >> c) & 1u)))
+                eval(std::integral_constant<bool, PER>());
+            else
+                eval(std::integral_constant<bool, false>());
 #pragma unroll
             for (int h = 0; h < FTILE / 64; ++h)
                 lk[h] |= (c >> 3) == h ? (uint64_t)m8 << ((c & 7) * 8) : 0ull;

@@ -1040,13 +1040,30 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
             // and split each chunk's positions.
             visited += (unsigned)__popc(any & ((1u << take) - 1u));
             const int nch = uni(npts >> 3);
-            unsigned M = 0;
+            // In a periodic box the minimum-image wrap of a difference only
+            // triggers beyond half a period: for a chunk with fl(q - lo) <= h
+            // and fl(q - hi) >= -h on every axis (the rounded difference is
+            // monotone in the point), no point of it wraps for this query, and
+            // its distances and bound are the open ones, bit for bit. W marks
+            // the chunks that may wrap; the periodic forms run only where some
+            // lane has one.
+            unsigned M = 0, W = 0;
             for (int c = 0; c < nch; ++c) {
                 const float4 *bx = cbox + c * 2;
                 const float4 blo = bx[0], bhi = bx[1];
-                const float lo2 = point_low2_m<PER>(me.x, me.y, me.z, blo.x, blo.y, blo.z, bhi.x,
-                                                    bhi.y, bhi.z, Lp);
-                M |= (act && lo2 <= kth) ? (1u << c) : 0u;
+                bool wrap = false;
+                if constexpr (PER)
+                    wrap = !(me.x - blo.x <= Lh && me.x - bhi.x >= -Lh && me.y - blo.y <= Lh &&
+                             me.y - bhi.y >= -Lh && me.z - blo.z <= Lh && me.z - bhi.z >= -Lh);
+                const float lo2 =
+                    (PER && __ballot(act && wrap))
+                        ? point_low2_m<PER>(me.x, me.y, me.z, blo.x, blo.y, blo.z, bhi.x, bhi.y,
+                                            bhi.z, Lp)
+                        : point_low2_m<false>(me.x, me.y, me.z, blo.x, blo.y, blo.z, bhi.x, bhi.y,
+                                              bhi.z, Lp);
+                const bool need = act && lo2 <= kth;
+                M |= need ? (1u << c) : 0u;
+                W |= need && wrap ? (1u << c) : 0u;
             }
             const int nit = uni(wave_max_i(__popc(M)));
             for (int it = 0; it < nit; ++it) {
@@ -1054,16 +1071,23 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
                 const int c = has ? __ffs((int)M) - 1 : 0;
                 M &= M - 1u;
                 const float thr = has ? kth : -1.0f;
+                auto eval = [&](auto per_const) {
+                    constexpr bool P = decltype(per_const)::value;
 #pragma unroll
-                for (int u = 0; u < 8 / SS; ++u) {
-                    const int j = tslot(c * 8 + u * SS + h);
-                    const float4 p = tile[j];
-                    const float dd = dist2_m<PER>(me.x, me.y, me.z, p.x, p.y, p.z, Lp, Lh);
-                    // written always, kept only if accepted (at most CH
-                    // positions per pop from qn <= CQ - CH: the slot exists)
-                    *qp = (uint8_t)j;
-                    qp += (dd <= thr && (!LO || dd >= lo_d)) ? 64 : 0;
-                }
+                    for (int u = 0; u < 8 / SS; ++u) {
+                        const int j = tslot(c * 8 + u * SS + h);
+                        const float4 p = tile[j];
+                        const float dd = dist2_m<P>(me.x, me.y, me.z, p.x, p.y, p.z, Lp, Lh);
+                        // written always, kept only if accepted (at most CH
+                        // positions per pop from qn <= CQ - CH: the slot exists)
+                        *qp = (uint8_t)j;
+                        qp += (dd <= thr && (!LO || dd >= lo_d)) ? 64 : 0;
+                    }
+                };
+                if (PER && __ballot(has && ((W >> c) & 1u)))
+                    eval(std::integral_constant<bool, PER>());
+                else
+                    eval(std::integral_constant<bool, false>());
                 steps += (unsigned)(8 / SS);
                 if (has) {
                     const int r = __float_as_int(cbox[c * 2].w);
