@@ -26,7 +26,7 @@
 namespace {
 
 __global__ void k_iota_n(int *__restrict__ a, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = (int64_t)blk_x() * bdim_x() + tid_x();
     if (i < n) a[i] = (int)i;
 }
 
@@ -34,13 +34,13 @@ __global__ void k_iota_n(int *__restrict__ a, int64_t n) {
 // a member; a point that stays a root of itself needs no update at all)
 __global__ __launch_bounds__(256) void k_init_min(const float4 *__restrict__ pts, int64_t n,
                                                   int *__restrict__ minidx) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = (int64_t)blk_x() * bdim_x() + tid_x();
     if (i < n) minidx[i] = __float_as_int(pts[i].w);
 }
 
 __global__ void k_node_b2(const int *__restrict__ node_set, int64_t L,
                           const float *__restrict__ b2_set, float *__restrict__ b2n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = (int64_t)blk_x() * bdim_x() + tid_x();
     if (i < L) b2n[i] = b2_set[node_set[i]];
 }
 
@@ -51,8 +51,8 @@ __global__ __launch_bounds__(64 * WPB) void k_fof_p2n(const int *__restrict__ pa
                                                  const int *__restrict__ whole_par,
                                                  int *__restrict__ whole, int *__restrict__ uf,
                                                  float b2, const float *__restrict__ b2n, float L) {
-    const int w = WPB == 1 ? 0 : uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
-    const int P = xcd_block(blockIdx.x, gridDim.x) * WPB + w;
+    const int w = WPB == 1 ? 0 : uni((int)(tid_x() >> 6)), lane = tid_x() & 63;
+    const int P = xcd_block(blk_x(), nblk_x()) * WPB + w;
     if (P >= n_par) return;
     const int c0 = par_spl[P], c1 = par_spl[P + 1];
     const int wp = whole_par ? whole_par[P] : 0;
@@ -70,8 +70,8 @@ __global__ __launch_bounds__(64 * WPB) void k_fof_p2n(const int *__restrict__ pa
 __global__ __launch_bounds__(64 * WPB) void k_fof_l2p(const Node *__restrict__ leaves, int n_leaves,
                                                  const int *__restrict__ whole,
                                                  int *__restrict__ uf) {
-    const int w = WPB == 1 ? 0 : uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
-    const int A = xcd_block(blockIdx.x, gridDim.x) * WPB + w;
+    const int w = WPB == 1 ? 0 : uni((int)(tid_x() >> 6)), lane = tid_x() & 63;
+    const int A = xcd_block(blk_x(), nblk_x()) * WPB + w;
     if (A >= n_leaves || !whole[A]) return;
     const Node a = leaves[A];
     for (int i = a.start + 1 + lane; i < a.start + a.count; i += 64) uf[i] = a.start;
@@ -119,8 +119,8 @@ __global__ __launch_bounds__(64 * WPB) void k_fof_step(
     unsigned long long *__restrict__ ctr, long long cap, unsigned long long *overflow, float L) {
     __shared__ Node s_tile[WPB][64];
     __shared__ int s_emit[WPB][64];
-    const int w = WPB == 1 ? 0 : uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
-    const int P = xcd_block(blockIdx.x, gridDim.x) * WPB + w;
+    const int w = WPB == 1 ? 0 : uni((int)(tid_x() >> 6)), lane = tid_x() & 63;
+    const int P = xcd_block(blk_x(), nblk_x()) * WPB + w;
     if (P >= n_par) return;
     const int2 sg = seg_in[P];
     const int2 *gl = list_in + uni(sg.x);
@@ -237,8 +237,8 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_fof(
     __shared__ Node s_nodes[WPB][FSB];
     __shared__ int s_offs[WPB][FSB + 1];
     __shared__ int s_root[WPB][64];
-    const int w = WPB == 1 ? 0 : uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
-    const int A = xcd_block(blockIdx.x, gridDim.x) * WPB + w;
+    const int w = WPB == 1 ? 0 : uni((int)(tid_x() >> 6)), lane = tid_x() & 63;
+    const int A = xcd_block(blk_x(), nblk_x()) * WPB + w;
     // a level of this attempt overflowed (it is rerun): nothing to do
     if (A >= n_leaves || *overflow) return;
     const Node a = leaves[A];
@@ -448,7 +448,7 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_fof(
 __global__ __launch_bounds__(256) void k_flatten_min(int *__restrict__ uf,
                                                      const float4 *__restrict__ pts, int64_t n,
                                                      int *__restrict__ minidx) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = (int64_t)blk_x() * bdim_x() + tid_x();
     const bool valid = i < n;
     const int lane = lane_id();
     int root = -1 - lane, v = INT_MAX;  // invalid lanes: a root of their own
@@ -483,7 +483,7 @@ __global__ __launch_bounds__(256) void k_flatten_min(int *__restrict__ uf,
 __global__ void k_labels(const int *__restrict__ uf, const float4 *__restrict__ pts, int64_t n,
                          const int *__restrict__ minidx, const int64_t *__restrict__ set_off,
                          int nsets, int32_t *__restrict__ label) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = (int64_t)blk_x() * bdim_x() + tid_x();
     if (i >= n) return;
     const int o = __float_as_int(pts[i].w);
     int base = 0;

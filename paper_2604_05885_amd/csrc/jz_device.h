@@ -157,6 +157,28 @@ __device__ __forceinline__ float point_low2_m(float qx, float qy, float qz, floa
 }
 
 // ---------------------------------------------------------------------------
+// Work-group and work-item indices read straight from the hardware registers
+// and the dispatch packet. The device library's accessors behind blockIdx,
+// threadIdx, gridDim and blockDim are not inlined into code built with a
+// different IEEE mode (the leaf-stage files): there they become calls, each
+// with a stack frame, and in the largest kernels the registers live across
+// them spill to scratch memory.
+__device__ __forceinline__ unsigned blk_x() { return __builtin_amdgcn_workgroup_id_x(); }
+__device__ __forceinline__ unsigned tid_x() { return __builtin_amdgcn_workitem_id_x(); }
+// dispatch packet: workgroup_size_x (16 bits) at byte 4, grid_size_x (work
+// items, 32 bits) at byte 12
+typedef const __attribute__((address_space(4))) uint16_t dispatch_u16;
+typedef const __attribute__((address_space(4))) uint32_t dispatch_u32;
+__device__ __forceinline__ unsigned bdim_x() {
+    return ((dispatch_u16 *)__builtin_amdgcn_dispatch_ptr())[2];
+}
+__device__ __forceinline__ unsigned nblk_x() {
+    const unsigned wg = ((dispatch_u16 *)__builtin_amdgcn_dispatch_ptr())[2];
+    const unsigned gs = ((dispatch_u32 *)__builtin_amdgcn_dispatch_ptr())[3];
+    return (gs + wg - 1) / wg;
+}
+
+// ---------------------------------------------------------------------------
 // wave64 primitives
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }

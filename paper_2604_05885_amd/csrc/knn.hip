@@ -117,7 +117,7 @@ __global__ __launch_bounds__(64) void k_find_long(const int2 *__restrict__ seg, 
                                                   int *__restrict__ ids_b,
                                                   unsigned long long *__restrict__ count_b) {
     const int lane = lane_id();
-    const int i = blockIdx.x * 64 + lane;
+    const int i = blk_x() * 64 + lane;
     const int len = i < n ? seg[i].y : 0;
     const bool la = len > min_len && len <= mid, lb = len > mid && len <= max_len;
     const uint64_t ma = __ballot(la), mb = __ballot(lb);
@@ -142,7 +142,7 @@ __global__ __launch_bounds__(64) void k_long_first(const int2 *__restrict__ seg,
                                                    int min_len, int *__restrict__ ids,
                                                    unsigned long long *__restrict__ count) {
     const int lane = lane_id();
-    const int i = blockIdx.x * 64 + lane;
+    const int i = blk_x() * 64 + lane;
     const bool l = i < n && seg[i].y > min_len;
     const uint64_t m = __ballot(l);
     if (!m) return;
@@ -164,9 +164,9 @@ __global__ __launch_bounds__(64 * NW) void k_sort_lists(int2 *__restrict__ list,
                                                         const unsigned long long *__restrict__ count) {
     __shared__ uint64_t s[CAP];
     constexpr int NT = 64 * NW;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int tid = tid_x(), lane = tid & 63, w = tid >> 6;
     const long long nl = (long long)*count;
-    for (long long jl = blockIdx.x; jl < nl; jl += gridDim.x) {
+    for (long long jl = blk_x(); jl < nl; jl += nblk_x()) {
         const int2 sg = seg[ids[jl]];
         int2 *g = list + sg.x;
         const int len = sg.y;
@@ -402,7 +402,7 @@ __global__ __launch_bounds__(64) void k_walk_items(const int *__restrict__ par_s
                                                    int2 *__restrict__ items,
                                                    unsigned long long *__restrict__ count) {
     const int lane = lane_id();
-    const int P = blockIdx.x * 64 + lane;
+    const int P = blk_x() * 64 + lane;
     int c0 = 0, nb = 0, cbe = cb;
     if (P < n_par) {
         c0 = par_spl[P];
@@ -442,10 +442,10 @@ __global__ __launch_bounds__(64 * WPB) void k_knn_step(
     // whole block is the scratch in which a longer list is sorted
     constexpr int RAW = LCAP + FCAP * (int)(sizeof(Node) / 8) + FCAP;
     __shared__ __align__(16) uint64_t s_raw[WPB][RAW];
-    const int w = WPB == 1 ? 0 : uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+    const int w = WPB == 1 ? 0 : uni((int)(tid_x() >> 6)), lane = tid_x() & 63;
     // work item I: receiving parent it.x, its children from it.y (at most
     // item_cb(cb, list length) of them)
-    const int I = xcd_block(blockIdx.x, gridDim.x) * WPB + w;
+    const int I = xcd_block(blk_x(), nblk_x()) * WPB + w;
     if (I >= (int)uni(*n_items)) return;
     const int2 it = items[I];
     const int P = uni(it.x);
@@ -779,10 +779,10 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
     __shared__ Node s_nodes[WPB][SB];
     __shared__ int s_offs[WPB][SB + 1];
     __shared__ int s_sc[WPB][SB];
-    const int w = WPB == 1 ? 0 : uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+    const int w = WPB == 1 ? 0 : uni((int)(tid_x() >> 6)), lane = tid_x() & 63;
     // the first waves take the leaves with lists longer than first_len (in
     // `first`), the others every leaf in order except those
-    const int wv = xcd_block(blockIdx.x, gridDim.x) * WPB + w;
+    const int wv = xcd_block(blk_x(), nblk_x()) * WPB + w;
     const int nfirst = (int)uni(*n_first);
     int A;
     if (wv < nfirst) {
@@ -854,7 +854,7 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
     // points is at most R (k = all passes' neighbours, so it bounds every
     // pass), so nothing farther is ever needed
     const float Rleaf = uni(rleaf[A]);
-    auto group_kth = [&]() {
+    auto group_kth = [&]() __attribute__((always_inline)) {
         float v = key_dist(best.get(K - 1));
         if (lgS >= 1) v = fminf(v, swap32_f(v));
         if (lgS >= 2) v = fminf(v, swap16_f(v));
@@ -863,7 +863,8 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
     // insert the queued candidates of every lane into its top-k: 8 at a time,
     // sorted in registers and merged (the busiest lane sets the trip count,
     // so batches of 8 cost far less than one insertion per candidate)
-    auto drain = [&]() {
+    // (inlined: outlined, the list it updates would live in scratch memory)
+    auto drain = [&]() __attribute__((always_inline)) {
         const int qn = (int)(qp - q0) >> 6;
         // a scalar trip count (a loop on a ballot compiles to a divergent
         // loop, whose exit handling copies the list every round)
@@ -895,7 +896,7 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
     float pf_rl = INFINITY;
     bool pf_ok = false;
     float4 pf_lo = make_float4(0, 0, 0, 0), pf_hi = pf_lo;  // the Node record's two halves
-    auto fetch = [&](int t0, int cnt) {
+    auto fetch = [&](int t0, int cnt) __attribute__((always_inline)) {
         pf_ok = lane < cnt && t0 + lane < len;
         if (pf_ok) {
             list_entry(staged, L, gl, t0 + lane, pf_src, pf_rl);
@@ -998,7 +999,7 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
         fetch(t + take, SB);
         wave_lds_sync();
         // the S lanes of a query take positions jj + h of every S-aligned step
-        auto scan = [&](auto s_const) {
+        auto scan = [&](auto s_const) __attribute__((always_inline)) {
             constexpr int SS = decltype(s_const)::value;
             if (t == 0) {
                 // the first source (one with r_low = 0) meets an empty top-k:
@@ -1071,7 +1072,7 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
                 const int c = has ? __ffs((int)M) - 1 : 0;
                 M &= M - 1u;
                 const float thr = has ? kth : -1.0f;
-                auto eval = [&](auto per_const) {
+                auto eval = [&](auto per_const) __attribute__((always_inline)) {
                     constexpr bool P = decltype(per_const)::value;
 #pragma unroll
                     for (int u = 0; u < 8 / SS; ++u) {
@@ -1184,8 +1185,8 @@ leaf_fn leaf_kernel(int k, int col, bool per) {
 
 namespace {
 __global__ __launch_bounds__(256) void k_zero_words(unsigned long long *__restrict__ p, size_t n) {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (size_t)gridDim.x * blockDim.x)
+    for (size_t i = (size_t)blk_x() * bdim_x() + tid_x(); i < n;
+         i += (size_t)nblk_x() * bdim_x())
         p[i] = 0;
 }
 }  // namespace
