@@ -217,14 +217,17 @@ class TorchAllocator:
 
     The library frees every block with the stream it was last used on; its
     calls are synchronous, so that work has finished when a block returns to
-    torch. ``live`` counts the blocks currently handed out.
+    torch. ``live`` counts the blocks currently handed out, ``live_bytes``
+    their sizes.
     """
 
     def __init__(self, device=None):
         import torch
         self.device = torch.cuda.current_device() if device is None else int(device)
         self.live = 0
+        self.live_bytes = 0
         self.allocs = 0
+        self._sizes = {}
         self._alloc_cb = Allocator._fields_[1][1](self._alloc)
         self._free_cb = Allocator._fields_[2][1](self._free)
         self.struct = Allocator(None, self._alloc_cb, self._free_cb)
@@ -236,6 +239,8 @@ class TorchAllocator:
         except Exception:  # out of memory: the library reports JZ_E_OOM
             return None
         self.live += 1
+        self.live_bytes += int(nbytes)
+        self._sizes[p] = int(nbytes)
         self.allocs += 1
         return p
 
@@ -243,6 +248,7 @@ class TorchAllocator:
         import torch
         torch.cuda.caching_allocator_delete(int(ptr))
         self.live -= 1
+        self.live_bytes -= self._sizes.pop(int(ptr), int(nbytes))
 
 
 _torch_allocators = {}

@@ -153,7 +153,7 @@ __global__ __launch_bounds__(256) void k_hist_scan(const uint32_t *__restrict__ 
 
 constexpr int RS_THREADS = 256;
 constexpr int RS_WAVES = RS_THREADS / 64;
-constexpr int RS_ITEMS = 16;
+constexpr int RS_ITEMS = 24;  // 6144 keys per tile: two tiles fill a CU's LDS
 constexpr int RS_TILE = RS_THREADS * RS_ITEMS;
 constexpr uint64_t FLAG_AGG = 1ull << 62;
 constexpr uint64_t FLAG_INC = 2ull << 62;

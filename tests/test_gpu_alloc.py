@@ -2,6 +2,8 @@
 torch's caching allocator gives the same results as the library's own pool,
 every block is returned, and an allocator that fails at any point of a call
 makes that call return JZ_E_OOM without leaking a block."""
+import gc
+
 import numpy as np
 import pytest
 
@@ -27,11 +29,20 @@ def test_torch_allocator_results_and_accounting(jz):
     d = torch.from_numpy(p).cuda()
     torch.cuda.synchronize()
     A = jz.TorchAllocator()
-    before = torch.cuda.memory_allocated()
-    with jz.jz_build(d, allocator=A) as t:
+    # tensors of earlier tests freed by the garbage collector meanwhile would
+    # lower torch's count: collect first and hold the collector off
+    gc.collect()
+    gc.disable()
+    try:
+        before = torch.cuda.memory_allocated()
+        t = jz.jz_build(d, allocator=A)
         held = t.size()
+        grown = torch.cuda.memory_allocated() - before
+    finally:
+        gc.enable()
+    with t:
         assert held >= 30000 * 16 and A.live > 0
-        assert torch.cuda.memory_allocated() - before >= held
+        assert A.live_bytes >= held and grown >= held
         i, d2 = t.knn(16)
         lab = t.fof(b)
         torch.cuda.synchronize()
