@@ -373,6 +373,23 @@ typedef struct jz_stats {
 /* Statistics of the tree and of its last kNN / FoF call. */
 JZ_API jz_status jz_tree_stats(const jz_tree *t, jz_stats *s);
 
+/* jz_knn and jz_fof on one tree in one call, the two running concurrently:
+ * both only read the tree, so the FoF half runs from a second host thread on a
+ * stream the library keeps per device, while the calling thread runs the kNN
+ * half on `stream`. Both start after the work already queued on `stream`, and
+ * work queued on `stream` afterwards starts after both. idx, dist2 and label
+ * receive exactly what jz_knn(t, k, idx, dist2) and jz_fof(t, b, label) write;
+ * the arguments are checked as those two calls check them (a joint tree:
+ * JZ_E_INVALID). knn_st and fof_st (HOST, each may be NULL) receive the
+ * statistics of each half, as jz_tree_stats reports them after that call
+ * alone; jz_tree_stats afterwards reports the kNN half. With a user allocator
+ * (jz_build's `alloc`), its callbacks may be called from both threads at once.
+ * Errors: the kNN half's status and message if it failed, else the FoF
+ * half's. Like jz_knn and jz_fof, the call returns when both halves are
+ * done. */
+JZ_API jz_status jz_knn_fof(jz_tree *t, int k, int32_t *idx, float *dist2, float b,
+                            int32_t *label, void *stream, jz_stats *knn_st, jz_stats *fof_st);
+
 /* Turn device-time measurement of the leaf stage and of whole calls on (1) or
  * off (0) for calls made by this thread. Off by default. */
 JZ_API void jz_set_profiling(int on);
@@ -392,7 +409,7 @@ JZ_API void jz_release_cached(void);
 /* Thread-local message of the last error (empty string if none). */
 JZ_API const char *jz_last_error(void);
 
-/* ABI version of this header (3). */
+/* ABI version of this header (4). */
 JZ_API int jz_abi_version(void);
 
 #ifdef __cplusplus

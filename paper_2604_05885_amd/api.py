@@ -123,6 +123,8 @@ _SIGS = {
                                 ctypes.POINTER(Allocator), ctypes.POINTER(_vp)]),
     "jz_knn": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp]),
     "jz_fof": (ctypes.c_int, [_vp, ctypes.c_float, _vp, _vp]),
+    "jz_knn_fof": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, ctypes.c_float, _vp, _vp,
+                                  ctypes.POINTER(Stats), ctypes.POINTER(Stats)]),
     "jz_tree_free": (None, [_vp]),
     "jz_build_joint": (ctypes.c_int, [_vp, ctypes.c_int64, _vp, ctypes.c_int64, _vp,
                                       ctypes.POINTER(BuildOpts), ctypes.POINTER(Allocator),
@@ -356,6 +358,33 @@ class Tree:
             _check(lib.jz_forest_fof(self.handle, bb.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
                                      ctypes.c_void_p(label.data_ptr()), _stream(stream)))
         return label
+
+    def knn_fof(self, k: int, b: float, idx=None, dist2=None, label=None, stream=None):
+        """kNN and FoF in one call, run concurrently (jz_knn_fof): (idx, dist2,
+        label) as :meth:`knn` and :meth:`fof` give them. The two halves'
+        statistics are kept in ``self.last_stats`` as (knn, fof) dicts."""
+        import torch
+        dev = torch.device("cuda", torch.cuda.current_device())
+        if idx is None:
+            idx = torch.empty((self.n, k), dtype=torch.int32, device=dev)
+        if dist2 is None:
+            dist2 = torch.empty((self.n, k), dtype=torch.float32, device=dev)
+        if label is None:
+            label = torch.empty(self.n, dtype=torch.int32, device=dev)
+        if tuple(idx.shape) != (self.n, k) or tuple(dist2.shape) != (self.n, k) or \
+                not idx.is_contiguous() or not dist2.is_contiguous() or \
+                idx.dtype != torch.int32 or dist2.dtype != torch.float32:
+            raise TypeError("idx / dist2 must be contiguous int32 / float32 of shape (n, k)")
+        if tuple(label.shape) != (self.n,) or label.dtype != torch.int32 or \
+                not label.is_contiguous():
+            raise TypeError("label must be a contiguous int32 tensor of shape (n,)")
+        ks, fs = Stats(), Stats()
+        _check(lib.jz_knn_fof(self.handle, int(k), ctypes.c_void_p(idx.data_ptr()),
+                              ctypes.c_void_p(dist2.data_ptr()), float(np.float32(b)),
+                              ctypes.c_void_p(label.data_ptr()), _stream(stream),
+                              ctypes.byref(ks), ctypes.byref(fs)))
+        self.last_stats = (ks.as_dict(), fs.as_dict())
+        return idx, dist2, label
 
     def size(self) -> int:
         """Device bytes the tree holds between calls (jz_tree_size)."""

@@ -10,6 +10,8 @@
 #include <map>
 #include <mutex>
 #include <new>
+#include <string>
+#include <thread>
 #include <tuple>
 #include <algorithm>
 #include <unordered_map>
@@ -225,6 +227,31 @@ struct DeviceGuard {
     }
 };
 
+// The stream the FoF half of jz_knn_fof runs on: one per device, created on
+// first use and kept until the process ends (the pool keeps, for blocks freed
+// on it, events recorded on it).
+hipStream_t side_stream(int dev, jz_status &st) {
+    static std::mutex m;
+    static hipStream_t streams[64] = {};
+    std::lock_guard<std::mutex> lk(m);
+    hipStream_t &x = streams[dev & 63];
+    if (!x) {
+        const hipError_t e = hipStreamCreateWithFlags(&x, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            x = nullptr;
+            st = jz_hip_fail(e, "hipStreamCreateWithFlags", __FILE__, __LINE__);
+        }
+    }
+    return x;
+}
+
+struct EventGuard {
+    hipEvent_t e = nullptr;
+    ~EventGuard() {
+        if (e && hipEventDestroy(e) != hipSuccess) (void)hipGetLastError();
+    }
+};
+
 }  // namespace
 
 jz_status check_opts(const jz_build_opts &o) {
@@ -420,6 +447,65 @@ jz_status jz_fof(jz_tree *t, float b, int32_t *label, void *stream) {
     return run_fof(t, b2.data(), label, (hipStream_t)stream);
 }
 
+// kNN and FoF only read the tree and write disjoint outputs, so the FoF half
+// runs from a second host thread on the library's side stream while this
+// thread runs the kNN half on `stream`: each half keeps its own host-side
+// rerun checks, and the walk levels of one, which fill few waves, overlap
+// the other's work. Both halves start after the work queued on `stream` and
+// `stream` waits for both.
+jz_status jz_knn_fof(jz_tree *t, int k, int32_t *idx, float *dist2, float b, int32_t *label,
+                     void *stream, jz_stats *knn_st, jz_stats *fof_st) {
+    g_err.clear();
+    if (!t) return jz_fail(JZ_E_INVALID, "tree is NULL");
+    if (t->n_src >= 0) return jz_fail(JZ_E_INVALID, "jz_knn_fof takes a tree from jz_build");
+    if (k < 1) return jz_fail(JZ_E_INVALID, "k must be >= 1");
+    if (k > JZ_MAX_K) return jz_fail(JZ_E_UNSUPPORTED, "k > %d is not supported", JZ_MAX_K);
+    if (!(b >= 0.0f) || !std::isfinite(b)) return jz_fail(JZ_E_INVALID, "b must be finite and >= 0");
+    if (t->n > 0 && (!idx || !dist2 || !label)) return jz_fail(JZ_E_INVALID, "output is NULL");
+    const int dev = t->ac.device;
+    DeviceGuard g(dev);
+    const hipStream_t s = (hipStream_t)stream;
+    jz_status st = JZ_OK;
+    const hipStream_t s2 = side_stream(dev, st);
+    if (!s2) return st;
+    EventGuard e_in, e_out;
+    JZ_HIP(hipEventCreateWithFlags(&e_in.e, hipEventDisableTiming));
+    JZ_HIP(hipEventCreateWithFlags(&e_out.e, hipEventDisableTiming));
+    JZ_HIP(hipEventRecord(e_in.e, s));
+    JZ_HIP(hipStreamWaitEvent(s2, e_in.e, 0));
+
+    jz_stats fst = t->st;  // the tree's own fields; run_fof fills the call's
+    const std::vector<float> b2(t->nsets, b * b);
+    const bool prof = g_prof;
+    jz_status f_status = JZ_OK;
+    std::string f_msg;
+    auto fof_half = [&]() {
+        g_prof = prof;  // (thread-local settings of the calling thread)
+        DeviceGuard g2(dev);
+        f_status = run_fof(t, b2.data(), label, s2, &fst);
+        if (f_status != JZ_OK) f_msg = g_err;
+    };
+    std::thread th;
+    bool threaded = true;
+    try {
+        th = std::thread(fof_half);
+    } catch (...) {
+        threaded = false;  // no thread to be had: the halves run one after the other
+    }
+    const jz_status k_status = run_knn(t, k, idx, dist2, s);
+    if (threaded) th.join();
+    else fof_half();
+    // `stream` waits for the FoF half whatever either half returned
+    const hipError_t e1 = hipEventRecord(e_out.e, s2);
+    const hipError_t e2 = e1 == hipSuccess ? hipStreamWaitEvent(s, e_out.e, 0) : e1;
+    if (knn_st) *knn_st = t->st;
+    if (fof_st) *fof_st = fst;
+    if (k_status != JZ_OK) return k_status;
+    if (f_status != JZ_OK) return jz_fail(f_status, "%s", f_msg.c_str());
+    if (e2 != hipSuccess) return jz_hip_fail(e2, "ordering the FoF half before later work", __FILE__, __LINE__);
+    return JZ_OK;
+}
+
 jz_status jz_forest_fof(jz_tree *t, const float *b, int32_t *label, void *stream) {
     g_err.clear();
     if (!t) return jz_fail(JZ_E_INVALID, "tree is NULL");
@@ -495,6 +581,6 @@ void jz_release_cached(void) {
 
 const char *jz_last_error(void) { return g_err.c_str(); }
 
-int jz_abi_version(void) { return 3; }
+int jz_abi_version(void) { return 4; }
 
 }  // extern "C"

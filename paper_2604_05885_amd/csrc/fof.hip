@@ -500,18 +500,20 @@ __global__ void k_labels(const int *__restrict__ uf, const float4 *__restrict__ 
 
 }  // namespace
 
-jz_status run_fof(jz_tree *t, const float *b2_set_host, int32_t *label, hipStream_t s) {
+jz_status run_fof(jz_tree *t, const float *b2_set_host, int32_t *label, hipStream_t s,
+                  jz_stats *st_out) {
+    jz_stats &st = st_out ? *st_out : t->st;
     const AllocCtx *ac = &t->ac;
     const int P = t->P;
     const int64_t n = t->n;
-    for (int p = 0; p <= JZ_MAX_PLANES; ++p) t->st.list_entries[p] = 0;
-    t->st.leaf_pairs = t->st.leaf_pairs_visited = 0;
-    t->st.evaluations = 0;
-    t->st.leaf_ms = t->st.total_ms = 0;
-    t->st.reruns = 0;
-    t->st.insert_rounds = t->st.tile_steps = 0;
-    t->st.lists_sorted_long = t->st.lists_unordered = 0;
-    for (int p = 0; p <= JZ_MAX_PLANES; ++p) t->st.lists_presorted[p][0] = t->st.lists_presorted[p][1] = 0;
+    for (int p = 0; p <= JZ_MAX_PLANES; ++p) st.list_entries[p] = 0;
+    st.leaf_pairs = st.leaf_pairs_visited = 0;
+    st.evaluations = 0;
+    st.leaf_ms = st.total_ms = 0;
+    st.reruns = 0;
+    st.insert_rounds = st.tile_steps = 0;
+    st.lists_sorted_long = st.lists_unordered = 0;
+    for (int p = 0; p <= JZ_MAX_PLANES; ++p) st.lists_presorted[p][0] = st.lists_presorted[p][1] = 0;
     if (n == 0) return JZ_OK;
 
     const bool sets = t->nsets > 1;
@@ -605,21 +607,21 @@ jz_status run_fof(jz_tree *t, const float *b2_set_host, int32_t *label, hipStrea
         if (overflow) {
             if (!t->opts.auto_regrow)
                 return jz_fail(JZ_E_CAPACITY, "FoF interaction list overflow; raise list_per_node");
-            t->st.reruns++;
+            st.reruns++;
             continue;
         }
         for (int p = 0; p < P; ++p) {
-            t->st.list_entries[p] = (int64_t)sum[p];
+            st.list_entries[p] = (int64_t)sum[p];
             cap_learn(CAP_FOF, 0, p, need[p] / (double)std::max<int64_t>(1, t->L[p]));
         }
-        t->st.leaf_pairs = t->st.list_entries[0];
-        t->st.evaluations = stat_sum(hc.data(), 0);
+        st.leaf_pairs = st.list_entries[0];
+        st.evaluations = stat_sum(hc.data(), 0);
         if (ev.on) {
             float ms = 0;
             JZ_HIP(hipEventElapsedTime(&ms, ev[1], ev[2]));
-            t->st.leaf_ms = ms;
+            st.leaf_ms = ms;
             JZ_HIP(hipEventElapsedTime(&ms, ev[0], ev[3]));
-            t->st.total_ms = ms;
+            st.total_ms = ms;
         }
         return JZ_OK;
     }

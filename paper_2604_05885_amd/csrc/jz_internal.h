@@ -144,7 +144,9 @@ jz_status source_counts(jz_tree *t, hipStream_t s);
 // level list, acquired top level first and released bottom level first.
 jz_status run_knn(jz_tree *t, int k, int32_t *idx, float *dist2, hipStream_t s,
                   const AllocCtx *scratch = nullptr);
-jz_status run_fof(jz_tree *t, const float *b2_set_host, int32_t *label, hipStream_t s);
+// run_fof writes its call statistics to `st_out` when given (else to t->st)
+jz_status run_fof(jz_tree *t, const float *b2_set_host, int32_t *label, hipStream_t s,
+                  jz_stats *st_out = nullptr);
 // the ranges jz_build_opts documents (JZ_E_INVALID with a message otherwise)
 jz_status check_opts(const jz_build_opts &o);
 

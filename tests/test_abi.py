@@ -14,7 +14,7 @@ def test_library_exports_every_header_symbol():
     for name in names:
         assert hasattr(api.lib, name), name
     assert set(names) == set(api._SIGS)  # the binding covers the whole header
-    assert api.lib.jz_abi_version() == 3
+    assert api.lib.jz_abi_version() == 4
 
 
 def test_default_opts():
@@ -45,6 +45,7 @@ def test_argument_validation_without_gpu():
         assert api.lib.jz_last_error()
     assert api.lib.jz_knn(None, 8, None, None, None) == api.JZ_E_INVALID
     assert api.lib.jz_fof(None, 0.1, None, None) == api.JZ_E_INVALID
+    assert api.lib.jz_knn_fof(None, 8, None, None, 0.1, None, None, None, None) == api.JZ_E_INVALID
     st = api.Stats()
     assert api.lib.jz_tree_stats(None, ctypes.byref(st)) == api.JZ_E_INVALID
     off = np.array([0, 5, 3], dtype=np.int64)

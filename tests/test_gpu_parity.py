@@ -392,3 +392,56 @@ def test_key_width_never_changes_results(jz, key_bits):
     assert_knn_equal(gi, gd, wi, wd, "key_bits=%d" % key_bits)
     lab, _ = gpu_fof(jz, p, b, key_bits=key_bits)
     assert np.array_equal(lab, wl), key_bits
+
+
+def test_knn_fof_in_one_call(jz):
+    """jz_knn_fof (kNN on the given stream, FoF concurrently on a second one)
+    gives the oracle's results and those of the two calls made one after the
+    other, with the same kNN statistics; a call whose lists overflow reruns its
+    half on its own; a stream that is not the default one is ordered
+    before and after both halves; argument errors are those of jz_knn and
+    jz_fof."""
+    p = inputs.clustered(30000, 24, 91)
+    b = inputs.linking_length(30000, 0.2)
+    wi, wd = oracle.knn_bf(p, 16)
+    wl = oracle.fof_bf(p, b)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        # (k = 11, so no capacity learned by other tests applies: the first call reruns)
+        for k, lpn in ((11, 1.0), (16, None)):
+            opts = jz.default_opts(list_per_node=lpn) if lpn else None
+            dev = to_dev(p)  # queued on s: the call must wait for the copy
+            with jz.jz_build(dev, opts, stream=s) as t:
+                gi, gd, gl = t.knn_fof(k, b, stream=s)
+                ks, fs = t.last_stats
+                assert t.stats()["evaluations"] == ks["evaluations"]
+                ri, rd = t.knn(k, stream=s)
+                ks2 = t.stats()
+                rl = t.fof(b, stream=s)
+                fs2 = t.stats()
+                s.synchronize()
+                gi, gd, gl = gi.cpu().numpy(), gd.cpu().numpy(), gl.cpu().numpy()
+                want_i, want_d = oracle.knn_bf(p, k) if k != 16 else (wi, wd)
+                assert_knn_equal(gi, gd, want_i, want_d, "knn_fof k=%d" % k)
+                assert np.array_equal(gl, wl)
+                assert np.array_equal(gi, ri.cpu().numpy())
+                assert np.array_equal(gd.view(np.uint32), rd.cpu().numpy().view(np.uint32))
+                assert np.array_equal(gl, rl.cpu().numpy())
+                for key in ("evaluations", "leaf_pairs", "list_entries", "nodes"):
+                    assert ks[key] == ks2[key], key
+                # (FoF's lists and evaluation counts depend on when unions
+                # land: pairs found already connected are dropped)
+                assert fs["nodes"] == fs2["nodes"] and fs["planes"] == fs2["planes"]
+                assert fs["evaluations"] > 0 and fs["leaf_pairs"] > 0
+                if lpn:  # (FoF capacities learned by earlier calls may spare its rerun)
+                    assert ks["reruns"] >= 1, ks["reruns"]
+    with jz.jz_build(to_dev(inputs.uniform(100, 1))) as t:
+        with pytest.raises(jz.JzError) as e:
+            t.knn_fof(257, 0.1)
+        assert e.value.status == jz.JZ_E_UNSUPPORTED
+        with pytest.raises(jz.JzError) as e:
+            t.knn_fof(4, -1.0)
+        assert e.value.status == jz.JZ_E_INVALID
+    with jz.jz_build(torch.zeros((0, 3), dtype=torch.float32, device="cuda")) as t:
+        gi, gd, gl = t.knn_fof(4, 0.1)
+        assert gi.shape == (0, 4) and gl.shape == (0,)
