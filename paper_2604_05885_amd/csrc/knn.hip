@@ -876,9 +876,11 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
             for (int u = 0; u < 8; ++u) {
                 // slots are read unconditionally (branches around the reads
                 // would make the compiler copy the list)
+                // (a slot past the lane's count holds a stale byte: still a
+                // tile position, and its key is replaced by the padding key)
                 const int slot = min(c + u, CQ - 1);
                 const int qv = q0[64 * slot];
-                const float4 s = tile[c + u < qn ? qv : 0];
+                const float4 s = tile[qv];
                 const float dd = dist2_m<PER>(me.x, me.y, me.z, s.x, s.y, s.z, Lp, Lh);
                 const double kk = key_of(dd, __float_as_int(s.w));
                 ch[u] = (c + u < qn && (!LO || kk > lo)) ? kk : pad;
@@ -1072,11 +1074,17 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_knn(
                 const int c = has ? __ffs((int)M) - 1 : 0;
                 M &= M - 1u;
                 const float thr = has ? kth : -1.0f;
+                // tslot(c * 8 + q) for q < 8 is (c * 8 | (c & 7)) ^ q, and
+                // q = u * SS + h = (u * SS) ^ h: one XOR per position
+                const int jb = (c * 8 | (c & 7)) ^ h;
+                // (the queue pointer is kept as an address, not as an offset
+                // from the lane's first slot, so no add is needed per write)
+                asm volatile("" : "+v"(qp));
                 auto eval = [&](auto per_const) __attribute__((always_inline)) {
                     constexpr bool P = decltype(per_const)::value;
 #pragma unroll
                     for (int u = 0; u < 8 / SS; ++u) {
-                        const int j = tslot(c * 8 + u * SS + h);
+                        const int j = jb ^ (u * SS);
                         const float4 p = tile[j];
                         const float dd = dist2_m<P>(me.x, me.y, me.z, p.x, p.y, p.z, Lp, Lh);
                         // written always, kept only if accepted (at most CH
