@@ -73,9 +73,11 @@ typedef struct jz_build_opts {
     int n_target;          /* stop adding planes when N / (N_max^(p)/2) < n_target. Default 1000. */
     int ngr;               /* top nodes per super node (NGR of Alg. 1). Default 32, range [1, 64]. */
     int key_bits;          /* Morton bits per dimension, range [1, 21]; 0 (default): automatic,
-                              ceil(log2(n) / 3) + 8 bits (at least 10, at most 21), i.e. cells
-                              far below the mean point spacing. Results never depend on it;
-                              fewer bits mean fewer radix-sort passes. */
+                              b = ceil(log2(n) / 3) + 5 bits (at least 10), i.e. cells 32 times
+                              finer than the mean point spacing, raised to the most that the
+                              radix passes b needs can hold (a pass sorts 8 bits of the key:
+                              13 bits and 5 passes at n = 2^24), at most 21. Results never
+                              depend on it; fewer bits mean fewer radix-sort passes. */
     float list_per_node;   /* initial interaction-list capacity in entries per node. Default 96.
                               With auto_regrow = 1 the library may start larger, from the list
                               sizes it has seen in this process. */

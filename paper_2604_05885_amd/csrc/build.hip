@@ -787,13 +787,17 @@ jz_status build_tree(jz_tree *t, const float *points, hipStream_t s) {
     if (n == 0) return JZ_OK;
 
     const int has_sets = t->nsets > 1;
-    // automatic key bits: 8 more per dimension than an even split of n
-    // points needs (cells well below the mean spacing), at most 21
+    // automatic key bits: 5 more per dimension than an even split of n
+    // points needs (cells 32 times finer than the mean spacing), raised to
+    // as many as the radix passes those need can hold (a pass sorts 8 key
+    // bits; set bits come first), at most 21
     int bits = o.key_bits;
     if (bits == 0) {
         int lg = 0;
         while (lg < 62 && ((int64_t)1 << lg) < n) ++lg;
-        bits = std::min(21, std::max(10, (lg + 2) / 3 + 8));
+        const int b0 = std::max(10, (lg + 2) / 3 + 5);
+        const int np = (3 * b0 + t->set_bits + 7) / 8;
+        bits = std::min(21, std::max(b0, (8 * np - t->set_bits) / 3));
     }
     const int max_bits = (63 - t->set_bits) / 3;
     if (bits > max_bits) bits = max_bits;

@@ -359,20 +359,27 @@ __global__ __launch_bounds__(64 * WPB) void k_leaf_fof(
             M &= M - 1u;
             const int real = has ? __float_as_int(cbox[c * 2].w) : 0;
             const int cfirst = __float_as_int(cbox[c * 2 + 1].w);
+            // the positions u that count, as a mask: u < real (a real point)
+            // and cfirst + u > my (a pair is taken from its lower point)
+            const unsigned okm = (0xffu >> (8 - real)) &
+                                 (0xffu << min(max(my - cfirst + 1, 0), 8));
+            // fslot(c * 8 + u) for u < 8 is (c * 8 | (c & 7)) ^ u
+            const int jb = c * 8 | (c & 7);
             unsigned m8 = 0;
-            auto eval = [&](auto per_const) {
+            auto eval = [&](auto per_const) __attribute__((always_inline)) {
                 constexpr bool P = decltype(per_const)::value;
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
-                    const float4 s = tile[fslot(c * 8 + u)];
+                    const float4 s = tile[jb ^ u];
                     const float dd = dist2_m<P>(me.x, me.y, me.z, s.x, s.y, s.z, L, Lh);
-                    m8 |= (u < real && cfirst + u > my && dd <= bb) ? (1u << u) : 0u;
+                    m8 |= dd <= bb ? (1u << u) : 0u;
                 }
             };
             if (PER && __ballot(has && ((W >> c) & 1u)))
                 eval(std::integral_constant<bool, PER>());
             else
                 eval(std::integral_constant<bool, false>());
+            m8 &= okm;
 #pragma unroll
             for (int h = 0; h < FTILE / 64; ++h)
                 lk[h] |= (c >> 3) == h ? (uint64_t)m8 << ((c & 7) * 8) : 0ull;

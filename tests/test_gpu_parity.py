@@ -379,7 +379,7 @@ def test_regularization_same_results_smaller_nodes(jz):
     assert leaves[1] > leaves[0], leaves
 
 
-@pytest.mark.parametrize("key_bits", [1, 4, 10, 21])
+@pytest.mark.parametrize("key_bits", [1, 4, 10, 13, 21])
 def test_key_width_never_changes_results(jz, key_bits):
     """Coarse Morton keys make many points share a key (equal keys are cut
     into aligned power-of-two runs of sorted positions); the automatic width
