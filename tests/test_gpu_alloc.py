@@ -66,6 +66,27 @@ def test_torch_allocator_results_and_accounting(jz):
     assert jz.torch_allocator().live == 0
 
 
+def test_torch_allocator_from_two_threads(jz):
+    """jz_knn_fof takes memory from the calling thread (kNN half) and from a
+    second thread of the library's (FoF half, on its own stream) at once:
+    the results are the oracle's, and every block is returned."""
+    p = inputs.clustered(30000, 16, 63)
+    b = inputs.linking_length(30000, 0.2)
+    d = torch.from_numpy(p).cuda()
+    wi, wd = oracle.knn_bf(p, 12)
+    wl = oracle.fof_bf(p, b)
+    A = jz.TorchAllocator()
+    for _ in range(2):
+        with jz.jz_build(d, allocator=A) as t:
+            i, d2, lab = t.knn_fof(12, b)
+            torch.cuda.synchronize()
+            assert np.array_equal(i.cpu().numpy(), wi)
+            assert np.array_equal(d2.cpu().numpy().view(np.uint32), wd.view(np.uint32))
+            assert np.array_equal(lab.cpu().numpy(), wl)
+        assert A.live == 0 and A.live_bytes == 0
+    assert A.allocs > 0
+
+
 class FailingAllocator:
     """torch's caching allocator, except that allocation number ``fail_at``
     (1-based, counted from ``arm()``) returns NULL."""
