@@ -225,11 +225,18 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+KERNEL_SOURCES = ("knn.hip", "jz_device.h")  # the leaf-kNN kernel and the device helpers it inlines
+
+
 def kernel_hash() -> str:
-    """sha256 of the leaf-kNN source file (ties traffic counters to a kernel version)."""
+    """sha256 over the leaf-kNN kernel's source files (ties traffic counters to
+    a kernel version)."""
     import hashlib
-    with open(os.path.join(ROOT, "paper_2604_05885_amd", "csrc", "knn.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2604_05885_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def copycal(args):
