@@ -445,3 +445,12 @@ def test_knn_fof_in_one_call(jz):
     with jz.jz_build(torch.zeros((0, 3), dtype=torch.float32, device="cuda")) as t:
         gi, gd, gl = t.knn_fof(4, 0.1)
         assert gi.shape == (0, 4) and gl.shape == (0,)
+    # lists too small and no regrow: the kNN half's error is returned (the
+    # FoF half's, if it failed too, is not)
+    q = inputs.uniform(8000, 23)
+    opts = jz.default_opts(list_per_node=1.0, auto_regrow=0)
+    with jz.jz_build(to_dev(q), opts) as t:
+        with pytest.raises(jz.JzError) as e:
+            t.knn_fof(16, inputs.linking_length(8000, 0.2))
+        assert e.value.status == jz.JZ_E_CAPACITY
+        assert "interaction list overflow" in str(e.value) and "FoF" not in str(e.value)
