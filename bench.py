@@ -4,7 +4,9 @@ One step = jz_build (z-order sort + tree planes) + jz_knn_fof(k, b) (kNN and
 FoF on the same tree, run concurrently on two streams; --serial: jz_knn then
 jz_fof) + jz_tree_free on a clustered synthetic point set already resident in HBM
 (60% of points in 4096 Gaussian clumps, 40% uniform background; the stand-in
-for the paper's cosmological snapshots). Prints one JSON line.
+for the paper's cosmological snapshots). The tree grows nodes 16-fold per plane
+in the concurrent schedule (the library's default of 8 with --serial). Prints
+one JSON line.
 
 value = N * steps / (wall time of the timed steps)  [points/s]
 
@@ -48,6 +50,15 @@ def parse():
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--period", type=float, default=0.0,
                     help="step mode: > 0 runs in the periodic cube [0, period)^3 (minimum image)")
+    ap.add_argument("--leaf-max", type=int, default=0,
+                    help="step mode: most points per leaf (0: the library default)")
+    ap.add_argument("--coarsen", type=int, default=0,
+                    help="step mode: node growth per plane (0: 16 with kNN and FoF concurrent, "
+                         "the library default with --serial)")
+    ap.add_argument("--n-target", type=int, default=0,
+                    help="step mode: plane stop rule's node count (0: the library default)")
+    ap.add_argument("--ngr", type=int, default=0,
+                    help="step mode: top nodes per super node (0: the library default)")
     ap.add_argument("--key-bits", type=int, default=0,
                     help="step mode: Morton key bits per dimension (0: the library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -103,6 +114,20 @@ def main():
         kw["period"] = args.period
     if args.key_bits > 0:
         kw["key_bits"] = args.key_bits
+    if args.leaf_max > 0:
+        kw["leaf_max"] = args.leaf_max
+    if args.coarsen > 0:
+        kw["coarsen"] = args.coarsen
+    elif not args.serial:
+        # node growth 16 per plane (three planes at 2^24 instead of four):
+        # with the two halves concurrent, the shorter kNN walk leaves the FoF
+        # half's tail to overlap the leaf kNN; one after the other, the
+        # library's default of 8 is the faster
+        kw["coarsen"] = 16
+    if args.n_target > 0:
+        kw["n_target"] = args.n_target
+    if args.ngr > 0:
+        kw["ngr"] = args.ngr
     opts = api.default_opts(**kw) if kw else None
 
     def step(ev=None):
@@ -185,6 +210,8 @@ def main():
                      "traffic": traffic, "evaluations": evals, "flops_per_eval": FLOPS_PER_EVAL,
                      "leaf_ms": leaf_avg},
         "breakdown": {"schedule": "serial" if args.serial else "kNN and FoF concurrent",
+                      "tree_opts": {f: getattr(opts if opts is not None else api.default_opts(), f)
+                                    for f in ("leaf_max", "coarsen", "n_target", "ngr", "key_bits")},
                       "build_ms": float(np.median(build_ms)),
                       "knn_fof_ms": float(np.median(knn_fof_ms)), "knn_ms": float(np.median(knn_ms)),
                       "fof_ms": float(np.median(fof_ms)), "knn_leaf_ms": leaf_avg,

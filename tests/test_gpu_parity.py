@@ -331,7 +331,8 @@ def test_forest_equals_standalone(jz):
 def test_full_size_clustered(jz, fp64_log):
     """N = 2^24 clustered (the benchmark workload): kNN k=16 on 2^14 sampled
     rows against brute force and in full against the exact kd-tree oracle; FoF
-    in full against the kd-tree oracle; binary64 cross-checks of the sampled
+    in full against the kd-tree oracle; the benchmark's concurrent call on its
+    tree (node growth 16) gives the same; binary64 cross-checks of the sampled
     kNN rows and of every FoF pair (reported, not asserted)."""
     n = 2 ** 24
     p = inputs.clustered(n, 4096, 2)
@@ -341,6 +342,15 @@ def test_full_size_clustered(jz, fp64_log):
         lab = t.fof(b)
         torch.cuda.synchronize()
         gi, gd, gl = idx.cpu().numpy(), d2.cpu().numpy(), lab.cpu().numpy()
+        del idx, d2, lab
+    # the benchmark's call: both halves concurrent, on a tree of node growth
+    # 16 per plane; the same results
+    with jz.jz_build(to_dev(p), jz.default_opts(coarsen=16)) as t:
+        idx, d2, lab = t.knn_fof(16, b)
+        torch.cuda.synchronize()
+        assert np.array_equal(idx.cpu().numpy(), gi)
+        assert np.array_equal(d2.cpu().numpy().view(np.uint32), gd.view(np.uint32))
+        assert np.array_equal(lab.cpu().numpy(), gl)
         del idx, d2, lab
     rows = np.random.default_rng(9).choice(n, 2 ** 14, replace=False)
     wi, wd = oracle.knn_bf(p, 16, rows=rows)
