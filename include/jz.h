@@ -50,7 +50,7 @@ typedef enum jz_status {
     JZ_E_NONFINITE = 2,    /* an input coordinate is NaN or infinite */
     JZ_E_UNSUPPORTED = 3,  /* k > JZ_MAX_K */
     JZ_E_CAPACITY = 4,     /* interaction list overflow with auto_regrow = 0 */
-    JZ_E_OOM = 5,          /* device allocation failed */
+    JZ_E_OOM = 5,          /* device allocation failed (jz_knn_fof: also host memory) */
     JZ_E_DEVICE = 6        /* a HIP runtime error */
 } jz_status;
 

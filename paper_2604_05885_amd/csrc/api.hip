@@ -479,10 +479,15 @@ jz_status jz_knn_fof(jz_tree *t, int k, int32_t *idx, float *dist2, float b, int
     const bool prof = g_prof;
     jz_status f_status = JZ_OK;
     std::string f_msg;
+    // (no exception may leave a thread: a failed host allocation becomes a status)
     auto fof_half = [&]() {
         g_prof = prof;  // (thread-local settings of the calling thread)
         DeviceGuard g2(dev);
-        f_status = run_fof(t, b2.data(), label, s2, &fst);
+        try {
+            f_status = run_fof(t, b2.data(), label, s2, &fst);
+        } catch (...) {
+            f_status = jz_fail(JZ_E_OOM, "host allocation failed in the FoF half");
+        }
         if (f_status != JZ_OK) f_msg = g_err;
     };
     std::thread th;
@@ -492,7 +497,12 @@ jz_status jz_knn_fof(jz_tree *t, int k, int32_t *idx, float *dist2, float b, int
     } catch (...) {
         threaded = false;  // no thread to be had: the halves run one after the other
     }
-    const jz_status k_status = run_knn(t, k, idx, dist2, s);
+    jz_status k_status;
+    try {
+        k_status = run_knn(t, k, idx, dist2, s);
+    } catch (...) {
+        k_status = jz_fail(JZ_E_OOM, "host allocation failed in the kNN half");
+    }
     if (threaded) th.join();
     else fof_half();
     // `stream` waits for the FoF half whatever either half returned
